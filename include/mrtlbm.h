@@ -1,0 +1,208 @@
+/*
+ * mrtlbm.h -- C ABI of the MI355X (gfx950) solver for steady anisotropic heat
+ * conduction in voxelised heterogeneous media by the D3Q7 multiple-relaxation-
+ * time lattice Boltzmann method of Fang, Gou, Zhang, Chen and Tao
+ * ("Numerical predictions of effective thermal conductivities for 3D
+ * four-directional braided composites using the lattice Boltzmann method").
+ *
+ * Conventions (every entry point):
+ *   - Grids are [nz][ny][nx], x fastest.  Node (i, j, k) is the centre of voxel
+ *     (i, j, k); phase interfaces and the outer walls lie on voxel faces, half
+ *     way between nodes (the half lattice division of Sec. 2.3).
+ *   - Pointers named *_dev are device pointers; *_host are host pointers.
+ *     All device memory is owned by the caller (e.g. torch tensors): the phase
+ *     grid, the workspace and every output.  The library owns only the opaque
+ *     host-side medium, a 256-byte pinned host staging buffer and its graphs.
+ *   - "real" means float for MRTLBM_F32 media and double for MRTLBM_F64 media.
+ *   - All device work is enqueued on the stream given at creation (NULL = the
+ *     default stream).  Calls that return host values synchronise that stream.
+ *   - No exception or abort crosses the ABI.  Every call returns an
+ *     mrtlbm_status (0 = OK, < 0 = error, > 0 = warning);
+ *     mrtlbm_last_error() gives a message for the calling thread.
+ *   - Lattice units: voxel edge = time step = 1.  A phase with physical
+ *     conductivity tensor k gets the lattice diffusivity D = s k (Eq. 13 with
+ *     rho c_p = 1 in every phase, Eq. 20), where one scale s per medium makes
+ *     the largest eigenvalue of tau - I/2 over all phases equal dmax.
+ *     Effective conductivities are returned in the units of k.
+ *   - A medium is not thread-safe; distinct media are independent.
+ */
+#ifndef MRTLBM_H
+#define MRTLBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MRTLBM_OK = 0,
+    MRTLBM_NOT_CONVERGED = 1,   /* warning: max_steps ran out; results are valid partials */
+    MRTLBM_E_ARG = -1,          /* bad argument, dims, phase id >= nphase, size mismatch  */
+    MRTLBM_E_TENSOR = -2,       /* a conductivity tensor is not symmetric positive definite */
+    MRTLBM_E_BC = -3,           /* bad boundary specification                             */
+    MRTLBM_E_HIP = -4,          /* a HIP runtime call failed                              */
+    MRTLBM_E_NONFINITE = -5,    /* the state holds NaN or Inf                             */
+    MRTLBM_E_DIVERGED = -6,     /* the residual grew by > 1e3 across checks               */
+    MRTLBM_E_WORKSPACE = -7     /* workspace too small or misaligned                      */
+} mrtlbm_status;
+
+typedef enum { MRTLBM_F32 = 0, MRTLBM_F64 = 1 } mrtlbm_precision;
+typedef enum { MRTLBM_PERIODIC = 0, MRTLBM_ADIABATIC = 1 } mrtlbm_side;
+typedef enum {
+    MRTLBM_TOL_MAXDT = 0, /* stop when max |T(t) - T(t-1)| at a check < tol                        */
+    MRTLBM_TOL_KEFF = 1   /* stop when |k_hot - k_cold| / k_mid < tol and k_mid moved < tol/10     */
+} mrtlbm_tol_kind;
+
+typedef struct mrtlbm_medium mrtlbm_medium;
+
+/*
+ * Observables of one streaming step t -> t+1 (Eq. 22 evaluated three ways):
+ *   keff_hot / keff_cold: wall link fluxes through the hot / cold Dirichlet
+ *       face, N_g Phi / (dT A s), A = nodes per face;
+ *   keff_vol: N_g <q_g> / (dT s), the volume mean of the node flux (Eqs.
+ *       15-16) of the distribution arriving at t+1;
+ *   keff = (keff_hot + keff_cold) / 2;
+ *   keff_col[a] = N_g <q_a> / (dT s): the gradient column of the effective
+ *       tensor (keff_col[grad_axis] == keff_vol);
+ *   resid = max over nodes of |T(t+1) - T(t)|;
+ *   temp_mean = mean T(t+1).
+ */
+typedef struct {
+    double keff, keff_hot, keff_cold, keff_vol;
+    double keff_col[3];
+    double resid;
+    double temp_mean;
+    long long steps;  /* steps taken by the medium when the values were taken */
+    int converged;
+    int nonfinite;    /* nodes whose T(t+1) is not finite */
+} mrtlbm_result;
+
+/* Thread-block shape of the step kernel: each thread updates `vec`
+ * consecutive x nodes; a block is bx x by threads over (x-vectors, rows).
+ * vec in {1, 2, 4} (nx % vec == 0), bx in {8, 16, 32, 64}, bx*by in [64, 256]
+ * and a multiple of 64, vec*bx >= 16. */
+typedef struct { int vec, bx, by; } mrtlbm_launch;
+
+/* Bytes of caller-owned device workspace a medium of these sizes needs
+ * (two state buffers of 7 reals per node, reduction partials and tables),
+ * or 0 for invalid sizes. */
+size_t mrtlbm_workspace_bytes(int nx, int ny, int nz, int nphase, mrtlbm_precision p);
+
+/*
+ * Create a medium (Sec. 2.2-2.3; Eqs. 12-13 for the per-phase tables).
+ *   phase_dev: uint8 [nz][ny][nx]; borrowed, must outlive the medium; every
+ *       id must be < nphase (checked on the device, MRTLBM_E_ARG otherwise).
+ *   k_host: [nphase][6] = (kxx, kyy, kzz, kxy, kxz, kyz), physical units;
+ *       copied.  Each tensor must be symmetric positive definite
+ *       (MRTLBM_E_TENSOR).  1 <= nphase <= 256.
+ *   workspace_dev: >= mrtlbm_workspace_bytes(...) bytes, 256-byte aligned,
+ *       caller-owned, must outlive the medium.
+ *   hip_stream: a hipStream_t, or NULL for the default stream.
+ * Defaults: dmax = 1, gradient along x with T = 1 on the x = 0 face and
+ * T = 0 on the far x face, periodic y and z, state not initialised.
+ */
+mrtlbm_status mrtlbm_create(int nx, int ny, int nz, const unsigned char *phase_dev,
+                            const double *k_host, int nphase, mrtlbm_precision p,
+                            void *workspace_dev, size_t workspace_bytes, void *hip_stream,
+                            mrtlbm_medium **out);
+
+/* Boundary conditions (Sec. 2.3, Eqs. 23-25).  grad_axis (0, 1, 2) gets
+ * isothermal walls: t_hot on its index-0 face and t_cold on its last face
+ * (Eq. 23, half-way anti-bounce-back); t_hot != t_cold.  side[a] for the two
+ * other axes: MRTLBM_PERIODIC (Eq. 25) or MRTLBM_ADIABATIC (Eq. 24 with zero
+ * flux, half-way bounce-back); side[grad_axis] is ignored.  Invalidates the
+ * state: call mrtlbm_init afterwards. */
+mrtlbm_status mrtlbm_set_bc(mrtlbm_medium *m, int grad_axis, double t_hot, double t_cold,
+                            const int side[3]);
+
+/* Relaxation scale: largest eigenvalue of tau - I/2 over all phases
+ * (Eq. 13; the paper keeps tau_ii in (0.5, 2)).  0 < dmax <= 1.5.
+ * Invalidates the state. */
+mrtlbm_status mrtlbm_set_scale(mrtlbm_medium *m, double dmax);
+
+/* Initial state (Eq. 6): every node at equilibrium with temperature
+ * t0_dev[z][y][x] (real), or with T = 0 if t0_dev is NULL.  With
+ * flags & 1 the flux part of a non-equilibrium start is added from central
+ * differences of t0 (Eq. 15 read backwards).  Resets the step counter. */
+mrtlbm_status mrtlbm_init(mrtlbm_medium *m, const void *t0_dev, int flags);
+
+/* Advance nsteps collide-and-stream steps (Eqs. 5, 8, 21, 23-25); async. */
+mrtlbm_status mrtlbm_step(mrtlbm_medium *m, long long nsteps);
+
+/*
+ * Iterate to steady state.  Every check_every steps (even, >= 2) the last
+ * step of the block evaluates the observables in FP64; the stop rule `kind`
+ * is tested on them.  Returns MRTLBM_OK when converged,
+ * MRTLBM_NOT_CONVERGED when max_steps ran out (out holds the last check),
+ * MRTLBM_E_NONFINITE / MRTLBM_E_DIVERGED on failure.  Synchronises.
+ */
+mrtlbm_status mrtlbm_solve(mrtlbm_medium *m, double tol, mrtlbm_tol_kind kind, long long max_steps,
+                           int check_every, mrtlbm_result *out);
+
+/* Observables of the next streaming step, computed without changing the
+ * state (see mrtlbm_result).  Synchronises. */
+mrtlbm_status mrtlbm_keff(mrtlbm_medium *m, mrtlbm_result *out);
+
+/* Temperature T(t) = sum_i f_i (Eq. 14) into t_dev (real [nz][ny][nx]); async. */
+mrtlbm_status mrtlbm_temperature(mrtlbm_medium *m, void *t_dev);
+
+/* Node heat flux of the distribution arriving at t+1 (Eqs. 15-16, Fourier's
+ * sign), q = -k grad T in units of k times temperature per voxel edge, into
+ * q_dev (real [3][nz][ny][nx]); async. */
+mrtlbm_status mrtlbm_flux(mrtlbm_medium *m, void *q_dev);
+
+/* Checkpoint / resume: copy the library's state (real [7][nz][ny][nx]; it is
+ * the post-collision distribution minus w_i T_lin(x), T_lin the linear
+ * profile between the two walls) out of or into the medium, device to
+ * device, on the medium's stream.  A resumed medium continues bit for bit.
+ * state_set also sets the step counter. */
+mrtlbm_status mrtlbm_state_get(mrtlbm_medium *m, void *f_dev);
+mrtlbm_status mrtlbm_state_set(mrtlbm_medium *m, const void *f_dev, long long steps);
+
+/* Scale s, steps taken, and the launch shape in use. */
+mrtlbm_status mrtlbm_info(const mrtlbm_medium *m, double *scale, long long *steps, mrtlbm_launch *launch);
+
+/* Choose the step kernel's block shape.  NULL restores the default. */
+mrtlbm_status mrtlbm_set_launch(mrtlbm_medium *m, const mrtlbm_launch *launch);
+
+/* Time every admissible block shape on this medium (hip events, a few
+ * steps each), keep the fastest, and record it in the text file cache_path
+ * (keyed by device architecture, sizes and precision; NULL = no file).
+ * Clobbers the state: call before mrtlbm_init.  Synchronises. */
+mrtlbm_status mrtlbm_autotune(mrtlbm_medium *m, const char *cache_path, mrtlbm_launch *best);
+
+/* Look the block shape up in a cache written by mrtlbm_autotune; returns
+ * MRTLBM_NOT_CONVERGED (a warning) and leaves the shape alone on a miss. */
+mrtlbm_status mrtlbm_load_tuned(mrtlbm_medium *m, const char *cache_path);
+
+/* Run nsteps plain steps bracketed by hip events on the medium's stream and
+ * return the elapsed milliseconds.  Synchronises. */
+mrtlbm_status mrtlbm_time_steps(mrtlbm_medium *m, long long nsteps, double *ms);
+
+void mrtlbm_destroy(mrtlbm_medium *m);
+const char *mrtlbm_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Batched many-cell solver                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Bytes of device workspace mrtlbm_batch_solve needs for these media. */
+size_t mrtlbm_batch_workspace_bytes(mrtlbm_medium *const *cells, int n);
+
+/*
+ * Solve n initialised media together.  Every step is one kernel launch that
+ * covers all still-active cells (a table of row tiles), and the steps between
+ * checks are replayed as one hip graph; a cell leaves the table when its own
+ * stop rule holds.  All cells must share the precision and the stream of
+ * cells[0].  out: [n].  Returns MRTLBM_OK when every cell converged,
+ * MRTLBM_NOT_CONVERGED if any ran out of steps.  Synchronises.
+ */
+mrtlbm_status mrtlbm_batch_solve(mrtlbm_medium *const *cells, int n, double tol, mrtlbm_tol_kind kind,
+                                 long long max_steps, int check_every, void *workspace_dev,
+                                 size_t workspace_bytes, mrtlbm_result *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRTLBM_H */

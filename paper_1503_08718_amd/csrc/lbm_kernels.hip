@@ -1,0 +1,513 @@
+// Device code of the D3Q7 MRT lattice Boltzmann solver for gfx950.
+//
+// One step (Eqs. 5, 8, 21, 23-25), fused per node x:
+//   pull   f_i(x) = g_i(x - e_i) from the state at t (Eq. 21; periodic wrap,
+//          Eq. 25), or on a wall link the reflected local population,
+//          f_i(x) = sgn * g_ibar(x) (Eq. 23 with sgn = -1, Eq. 24 with sgn = +1),
+//          then add +-h on the gradient-axis pair;
+//   collide with tau_0 = tau_4 = tau_5 = tau_6 = 1 (Sec. 2.2 sets them to unity):
+//          the moments of Eq. 11 relax to (T, jhat, 3T/4, 0, 0) with
+//          jhat = (I - tau^-1) j, so the post-collision state is
+//          g_0 = T/4 and g_{2a+1,2a+2} = T/8 +- jhat_a / 2;
+//   push   the 7 outputs to the state at t+1.
+// g_i = f_hat_i - w_i T_lin(x) is the post-collision distribution minus the
+// equilibrium of the linear profile T_lin between the two isothermal walls.
+// The scheme is linear and P w = w, so this shift is exact: interior
+// streaming along the gradient axis gains +-w dT/N_g = +-h and the wall
+// terms eps (T_w - T_lin(node)) of Eq. 23 become +-h as well.  The stored
+// numbers are deviations from a known field, which keeps FP32 round-off
+// relative to the (small) deviation and flux rather than to T itself.
+//
+// Memory layout: structure of arrays, population-major [7][nz][ny][nx], x
+// fastest.  Every population value is pulled by exactly one node, so a step
+// reads 7 reals + 1 phase byte and writes 7 reals per node, each once.
+// A thread owns `VEC` consecutive x nodes of one row: all 7 streams are
+// aligned vector loads/stores, and the two x-moving populations take their
+// single out-of-vector element from the neighbouring lane (ds_bpermute), so no
+// unaligned access is issued.
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "lbm_internal.h"
+
+namespace mrt {
+
+template <typename real, int VEC>
+struct Vec {
+    real v[VEC];
+};
+
+template <typename real, int VEC>
+__device__ __forceinline__ Vec<real, VEC> vload(const real *__restrict__ p) {
+    Vec<real, VEC> r;
+    if constexpr (VEC == 1) {
+        r.v[0] = p[0];
+    } else {
+        typedef real vt __attribute__((ext_vector_type(VEC)));
+        vt t = *reinterpret_cast<const vt *>(p);
+#pragma unroll
+        for (int i = 0; i < VEC; i++) r.v[i] = t[i];
+    }
+    return r;
+}
+
+template <typename real, int VEC>
+__device__ __forceinline__ void vstore(real *__restrict__ p, const Vec<real, VEC> &r) {
+    if constexpr (VEC == 1) {
+        p[0] = r.v[0];
+    } else {
+        typedef real vt __attribute__((ext_vector_type(VEC)));
+        vt t;
+#pragma unroll
+        for (int i = 0; i < VEC; i++) t[i] = r.v[i];
+        *reinterpret_cast<vt *>(p) = t;
+    }
+}
+
+template <int VEC>
+__device__ __forceinline__ void load_phase(const uint8_t *__restrict__ p, int *out) {
+    if constexpr (VEC == 4) {
+        uint32_t w = *reinterpret_cast<const uint32_t *>(p);
+        out[0] = w & 0xff; out[1] = (w >> 8) & 0xff; out[2] = (w >> 16) & 0xff; out[3] = w >> 24;
+    } else if constexpr (VEC == 2) {
+        uint32_t w = *reinterpret_cast<const uint16_t *>(p);
+        out[0] = w & 0xff; out[1] = w >> 8;
+    } else {
+        out[0] = p[0];
+    }
+}
+
+// FP64 accumulators of the check step
+struct Acc {
+    double v[NRED];
+    __device__ void zero() {
+#pragma unroll
+        for (int i = 0; i < NRED; i++) v[i] = 0.0;
+    }
+};
+
+// MODE 0: step; 1: step + observables; 2: observables only; 3: as 2 + flux field
+template <typename real, int VEC, int MODE>
+__device__ __forceinline__ void node_update(const Cell<real> &c, const real *__restrict__ tab, int xv, int y, int z,
+                                            bool active, int tx, int bx, Acc &acc, real *__restrict__ qout,
+                                            real qscale) {
+    const long long N = c.N;
+    const int nx = c.nx, ny = c.ny, nz = c.nz;
+    const int x0 = xv * VEC;
+    const long long base = ((long long)z * ny + y) * nx + x0;
+    const real *__restrict__ s = c.src;
+
+    // neighbour rows/planes; on a non-periodic wall redirect to the opposite
+    // population of the node itself (the reflected link)
+    int ym = y - 1, yp = y + 1, pym = 3, pyp = 4;
+    const bool ylo = (y == 0), yhi = (y == ny - 1);
+    if (ylo) { if (c.per[1]) ym = ny - 1; else { ym = y; pym = 4; } }
+    if (yhi) { if (c.per[1]) yp = 0; else { yp = y; pyp = 3; } }
+    int zm = z - 1, zp = z + 1, pzm = 5, pzp = 6;
+    const bool zlo = (z == 0), zhi = (z == nz - 1);
+    if (zlo) { if (c.per[2]) zm = nz - 1; else { zm = z; pzm = 6; } }
+    if (zhi) { if (c.per[2]) zp = 0; else { zp = z; pzp = 5; } }
+
+    Vec<real, VEC> c0 = vload<real, VEC>(s + base);
+    Vec<real, VEC> a1 = vload<real, VEC>(s + N + base);
+    Vec<real, VEC> a2 = vload<real, VEC>(s + 2 * N + base);
+    Vec<real, VEC> b3 = vload<real, VEC>(s + pym * N + ((long long)z * ny + ym) * nx + x0);
+    Vec<real, VEC> b4 = vload<real, VEC>(s + pyp * N + ((long long)z * ny + yp) * nx + x0);
+    Vec<real, VEC> b5 = vload<real, VEC>(s + pzm * N + ((long long)zm * ny + y) * nx + x0);
+    Vec<real, VEC> b6 = vload<real, VEC>(s + pzp * N + ((long long)zp * ny + y) * nx + x0);
+    int ph[VEC];
+    load_phase<VEC>(c.phase + base, ph);
+    Vec<real, VEC> o3, o4, o5, o6;
+    if constexpr (MODE != 0) {  // own post-collision populations: T(t) for the residual
+        o3 = vload<real, VEC>(s + 3 * N + base);
+        o4 = vload<real, VEC>(s + 4 * N + base);
+        o5 = vload<real, VEC>(s + 5 * N + base);
+        o6 = vload<real, VEC>(s + 6 * N + base);
+    }
+
+    // x exchange inside the wave: my last g1 feeds the next lane's first
+    // node, my first g2 feeds the previous lane's last node
+    const int lane = __lane_id();
+    const bool row_in_chunk = (c.nxv <= bx);
+    int srcL = (tx > 0) ? lane - 1 : lane + (c.nxv - 1);
+    int srcR = (tx < bx - 1 && xv < c.nxv - 1) ? lane + 1 : lane - (c.nxv - 1);
+    srcL = min(max(srcL, 0), 63);
+    srcR = min(max(srcR, 0), 63);
+    const real gotL = __shfl(a1.v[VEC - 1], srcL, 64);
+    const real gotR = __shfl(a2.v[0], srcR, 64);
+    real left, right;
+    const real hx = c.h[0], hy = c.h[1], hz = c.h[2];
+    real rawHotX = 0, rawColdX = 0;
+    if (x0 == 0) {
+        if (c.per[0]) left = row_in_chunk ? gotL : s[N + base + nx - 1];
+        else { rawHotX = a2.v[0]; left = c.sgn[0] * a2.v[0]; }
+    } else {
+        left = (tx > 0) ? gotL : s[N + base - 1];
+    }
+    if (x0 + VEC == nx) {
+        if (c.per[0]) right = row_in_chunk ? gotR : s[2 * N + base - x0];
+        else { rawColdX = a1.v[VEC - 1]; right = c.sgn[0] * a1.v[VEC - 1]; }
+    } else {
+        right = (tx < bx - 1) ? gotR : s[2 * N + base + VEC];
+    }
+    const real sy3 = (ylo && !c.per[1]) ? c.sgn[1] : real(1);
+    const real sy4 = (yhi && !c.per[1]) ? c.sgn[1] : real(1);
+    const real sz5 = (zlo && !c.per[2]) ? c.sgn[2] : real(1);
+    const real sz6 = (zhi && !c.per[2]) ? c.sgn[2] : real(1);
+
+    Vec<real, VEC> out[Q];
+#pragma unroll
+    for (int v = 0; v < VEC; v++) {
+        const real f0 = c0.v[v];
+        const real f1 = (v == 0 ? left : a1.v[v - 1]) + hx;
+        const real f2 = (v == VEC - 1 ? right : a2.v[v + 1]) - hx;
+        const real f3 = sy3 * b3.v[v] + hy;
+        const real f4 = sy4 * b4.v[v] - hy;
+        const real f5 = sz5 * b5.v[v] + hz;
+        const real f6 = sz6 * b6.v[v] - hz;
+        const real T = f0 + f1 + f2 + f3 + f4 + f5 + f6;
+        const real jx = f1 - f2, jy = f3 - f4, jz = f5 - f6;
+        const real *tb = tab + ph[v] * TABW;  // half of (I - tau^-1)
+        const real hjx = tb[0] * jx + tb[3] * jy + tb[4] * jz;
+        const real hjy = tb[3] * jx + tb[1] * jy + tb[5] * jz;
+        const real hjz = tb[4] * jx + tb[5] * jy + tb[2] * jz;
+        const real t8 = T * real(0.125);
+        out[0].v[v] = T * real(0.25);
+        out[1].v[v] = t8 + hjx;
+        out[2].v[v] = t8 - hjx;
+        out[3].v[v] = t8 + hjy;
+        out[4].v[v] = t8 - hjy;
+        out[5].v[v] = t8 + hjz;
+        out[6].v[v] = t8 - hjz;
+        if constexpr (MODE != 0) {
+            if (active) {
+                const real Told = c0.v[v] + a1.v[v] + a2.v[v] + o3.v[v] + o4.v[v] + o5.v[v] + o6.v[v];
+                const double dT = fabs((double)T - (double)Told);
+                const double qx = 0.5 * (double)jx + (double)hjx;
+                const double qy = 0.5 * (double)jy + (double)hjy;
+                const double qz = 0.5 * (double)jz + (double)hjz;
+                acc.v[R_QX] += qx;
+                acc.v[R_QY] += qy;
+                acc.v[R_QZ] += qz;
+                acc.v[R_TSUM] += (double)T;
+                if (!(dT <= 1e300)) acc.v[R_NONFINITE] += 1.0;
+                else acc.v[R_RESID] = fmax(acc.v[R_RESID], dT);
+                if constexpr (MODE == 3) {
+                    const long long i = base + v;
+                    qout[i] = (real)(qx * (double)qscale);
+                    qout[N + i] = (real)(qy * (double)qscale);
+                    qout[2 * N + i] = (real)(qz * (double)qscale);
+                }
+            }
+        }
+    }
+
+    if constexpr (MODE != 0) {
+        if (active) {
+            // wall link fluxes through the isothermal faces:
+            // hot:  eps (T_hot - T_lin(0)) - 2 g_out = h - 2 g_out
+            // cold: 2 g_out + eps (T_lin(n-1) - T_cold) = 2 g_out + h
+            const int g = c.gaxis;
+            const double hg = (double)c.h[g];
+            if (g == 0) {
+                if (x0 == 0) acc.v[R_PHI_HOT] += hg - 2.0 * (double)rawHotX;
+                if (x0 + VEC == nx) acc.v[R_PHI_COLD] += 2.0 * (double)rawColdX + hg;
+            } else if (g == 1) {
+                if (ylo) for (int v = 0; v < VEC; v++) acc.v[R_PHI_HOT] += hg - 2.0 * (double)b3.v[v];
+                if (yhi) for (int v = 0; v < VEC; v++) acc.v[R_PHI_COLD] += 2.0 * (double)b4.v[v] + hg;
+            } else {
+                if (zlo) for (int v = 0; v < VEC; v++) acc.v[R_PHI_HOT] += hg - 2.0 * (double)b5.v[v];
+                if (zhi) for (int v = 0; v < VEC; v++) acc.v[R_PHI_COLD] += 2.0 * (double)b6.v[v] + hg;
+            }
+        }
+    }
+
+    if constexpr (MODE <= 1) {
+        if (active) {
+            real *__restrict__ d = c.dst;
+#pragma unroll
+            for (int i = 0; i < Q; i++) vstore<real, VEC>(d + i * N + base, out[i]);
+        }
+    }
+}
+
+template <typename real>
+__device__ __forceinline__ void load_table(const Cell<real> &c, real *tab) {
+    const int n = c.nphase * TABW;
+    for (int i = threadIdx.y * blockDim.x + threadIdx.x; i < n; i += blockDim.x * blockDim.y) tab[i] = c.tab[i];
+    __syncthreads();
+}
+
+template <typename real, int VEC>
+__global__ void __launch_bounds__(256) k_step(Cell<real> c) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    real *tab = reinterpret_cast<real *>(smem_raw);
+    load_table(c, tab);
+    const int tx = threadIdx.x, bx = blockDim.x;
+    int xv = blockIdx.x * bx + tx;
+    int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    const bool active = (xv < c.nxv) && (y < c.ny);
+    xv = min(xv, c.nxv - 1);
+    y = min(y, c.ny - 1);
+    Acc dummy;
+    node_update<real, VEC, 0>(c, tab, xv, y, z, active, tx, bx, dummy, nullptr, real(0));
+}
+
+// deterministic block reduction of the 8 accumulators (sums, one max)
+__device__ __forceinline__ void block_reduce_store(Acc &acc, double *out) {
+    __shared__ double red[16][NRED];
+#pragma unroll
+    for (int k = 0; k < NRED; k++) {
+        double v = acc.v[k];
+        for (int off = 32; off >= 1; off >>= 1) {
+            double o = __shfl_xor(v, off, 64);
+            v = (k == R_RESID) ? fmax(v, o) : v + o;
+        }
+        acc.v[k] = v;
+    }
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const int wave = tid >> 6, nw = (blockDim.x * blockDim.y + 63) >> 6;
+    if ((tid & 63) == 0)
+        for (int k = 0; k < NRED; k++) red[wave][k] = acc.v[k];
+    __syncthreads();
+    if (tid < NRED) {
+        double v = red[0][tid];
+        for (int w = 1; w < nw; w++) v = (tid == R_RESID) ? fmax(v, red[w][tid]) : v + red[w][tid];
+        out[tid] = v;
+    }
+}
+
+// Observables (and optionally the step): the grid covers x and y like the
+// step kernel; each block walks `zper` consecutive planes so that the number
+// of partials stays small and the summation order is fixed.
+template <typename real, int VEC, int MODE>
+__global__ void __launch_bounds__(256) k_check(Cell<real> c, int zper, double *partials, real *qout, real qscale) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    real *tab = reinterpret_cast<real *>(smem_raw);
+    load_table(c, tab);
+    const int tx = threadIdx.x, bx = blockDim.x;
+    int xv = blockIdx.x * bx + tx;
+    int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const bool active = (xv < c.nxv) && (y < c.ny);
+    xv = min(xv, c.nxv - 1);
+    y = min(y, c.ny - 1);
+    Acc acc;
+    acc.zero();
+    const int z0 = blockIdx.z * zper, z1 = min(c.nz, z0 + zper);
+    for (int z = z0; z < z1; z++) node_update<real, VEC, MODE>(c, tab, xv, y, z, active, tx, bx, acc, qout, qscale);
+    const long long b = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    block_reduce_store(acc, partials + b * NRED);
+}
+
+__global__ void __launch_bounds__(256) k_reduce(const double *__restrict__ partials, int nparts, double *final8) {
+    __shared__ double red[256][NRED];
+    const int t = threadIdx.x;
+    double v[NRED];
+    for (int k = 0; k < NRED; k++) v[k] = 0.0;
+    for (int i = t; i < nparts; i += 256)
+        for (int k = 0; k < NRED; k++) {
+            double p = partials[(long long)i * NRED + k];
+            v[k] = (k == R_RESID) ? fmax(v[k], p) : v[k] + p;
+        }
+    for (int k = 0; k < NRED; k++) red[t][k] = v[k];
+    __syncthreads();
+    for (int stride = 128; stride >= 1; stride >>= 1) {
+        if (t < stride)
+            for (int k = 0; k < NRED; k++)
+                red[t][k] = (k == R_RESID) ? fmax(red[t][k], red[t + stride][k]) : red[t][k] + red[t + stride][k];
+        __syncthreads();
+    }
+    if (t < NRED) final8[t] = red[0][t];
+}
+
+// T_lin at node index i of the gradient axis: walls at -1/2 and n - 1/2
+__device__ __forceinline__ double t_lin(int i, int n, double t_hot, double dT) {
+    return t_hot - (i + 0.5) * dT / n;
+}
+
+template <typename real>
+__global__ void k_init(Cell<real> c, real *state, const real *t0, int flags, double t_hot, double dT) {
+    const long long n = c.N;
+    const int ext[3] = {c.nx, c.ny, c.nz};
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % c.nx);
+        const long long r = i / c.nx;
+        const int y = (int)(r % c.ny), z = (int)(r / c.ny);
+        const int pos[3] = {x, y, z};
+        const int g = c.gaxis;
+        const double tl = t_lin(pos[g], ext[g], t_hot, dT);
+        const double T = t0 ? (double)t0[i] : 0.0;
+        const double dev = T - tl;
+        double jh[3] = {0.0, 0.0, 0.0};
+        if ((flags & 1) && t0) {
+            // grad T by central differences; walls: isothermal value at the
+            // half-way plane, adiabatic mirror, periodic wrap
+            double grad[3];
+            const long long stride[3] = {1, c.nx, (long long)c.nx * c.ny};
+            for (int a = 0; a < 3; a++) {
+                double lo, hi, dist = 2.0;
+                const int p = pos[a];
+                if (p > 0) lo = t0[i - stride[a]];
+                else if (c.per[a]) lo = t0[i + (long long)(ext[a] - 1) * stride[a]];
+                else if (a == g) { lo = t_hot; dist -= 0.5; }
+                else lo = T;
+                if (p < ext[a] - 1) hi = t0[i + stride[a]];
+                else if (c.per[a]) hi = t0[i - (long long)(ext[a] - 1) * stride[a]];
+                else if (a == g) { hi = t_hot - dT; dist -= 0.5; }
+                else hi = T;
+                grad[a] = (hi - lo) / dist;
+            }
+            // pre-collision j = -eps tau grad T (Eq. 15); jhat = (I - tau^-1) j
+            // = -eps (tau - I) grad T
+            const real *tb = c.tab + c.phase[i] * TABW + 6;  // tau - I
+            const double m[3][3] = {{tb[0], tb[3], tb[4]}, {tb[3], tb[1], tb[5]}, {tb[4], tb[5], tb[2]}};
+            for (int a = 0; a < 3; a++) jh[a] = -0.25 * (m[a][0] * grad[0] + m[a][1] * grad[1] + m[a][2] * grad[2]);
+        }
+        state[i] = (real)(0.25 * dev);
+        for (int a = 0; a < 3; a++) {
+            state[(2 * a + 1) * n + i] = (real)(0.125 * dev + 0.5 * jh[a]);
+            state[(2 * a + 2) * n + i] = (real)(0.125 * dev - 0.5 * jh[a]);
+        }
+    }
+}
+
+template <typename real>
+__global__ void k_temperature(Cell<real> c, const real *__restrict__ state, real *__restrict__ t_out, double t_hot,
+                              double dT) {
+    const long long n = c.N;
+    const int ext[3] = {c.nx, c.ny, c.nz};
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % c.nx);
+        const long long r = i / c.nx;
+        const int pos[3] = {x, (int)(r % c.ny), (int)(r / c.ny)};
+        real acc = state[i];
+        for (int q = 1; q < Q; q++) acc += state[q * n + i];
+        t_out[i] = (real)((double)acc + t_lin(pos[c.gaxis], ext[c.gaxis], t_hot, dT));
+    }
+}
+
+__global__ void k_phase_max(const uint8_t *__restrict__ phase, long long n, int *block_max) {
+    __shared__ int red[256];
+    int m = 0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        m = max(m, (int)phase[i]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) block_max[blockIdx.x] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+
+static inline dim3 step_grid(int nxv, int ny, int nz, const Launch &L) {
+    return dim3((nxv + L.bx - 1) / L.bx, (ny + L.by - 1) / L.by, nz);
+}
+
+template <typename real>
+hipError_t launch_step(const Cell<real> &c, const Launch &L, hipStream_t s) {
+    Cell<real> cc = c;
+    cc.nxv = c.nx / L.vec;
+    const dim3 grid = step_grid(cc.nxv, c.ny, c.nz, L), block(L.bx, L.by);
+    const size_t sh = sizeof(real) * TABW * c.nphase;
+    switch (L.vec) {
+        case 4: hipLaunchKernelGGL((k_step<real, 4>), grid, block, sh, s, cc); break;
+        case 2: hipLaunchKernelGGL((k_step<real, 2>), grid, block, sh, s, cc); break;
+        default: hipLaunchKernelGGL((k_step<real, 1>), grid, block, sh, s, cc); break;
+    }
+    return hipGetLastError();
+}
+
+static inline int check_zper(int gx, int gy, int nz) {
+    const long long xy = (long long)gx * gy;
+    long long zb = (2048 + xy - 1) / xy;  // aim at ~2048 blocks
+    if (zb > nz) zb = nz;
+    if (zb < 1) zb = 1;
+    return (int)((nz + zb - 1) / zb);
+}
+
+template <typename real>
+int check_blocks(const Cell<real> &c, const Launch &L) {
+    const int nxv = c.nx / L.vec;
+    const dim3 g = step_grid(nxv, c.ny, c.nz, L);
+    const int zper = check_zper(g.x, g.y, c.nz);
+    return g.x * g.y * ((c.nz + zper - 1) / zper);
+}
+
+template <typename real, int VEC>
+static void launch_check_vec(const Cell<real> &c, dim3 grid, dim3 block, size_t sh, int zper, int mode, double *parts,
+                             real *q, real qs, hipStream_t s) {
+    switch (mode) {
+        case 1: hipLaunchKernelGGL((k_check<real, VEC, 1>), grid, block, sh, s, c, zper, parts, q, qs); break;
+        case 2: hipLaunchKernelGGL((k_check<real, VEC, 2>), grid, block, sh, s, c, zper, parts, q, qs); break;
+        default: hipLaunchKernelGGL((k_check<real, VEC, 3>), grid, block, sh, s, c, zper, parts, q, qs); break;
+    }
+}
+
+template <typename real>
+hipError_t launch_check(const Cell<real> &c, const Launch &L, int mode, double *partials, int *nblocks_out, real *q_out,
+                        double qscale, hipStream_t s) {
+    Cell<real> cc = c;
+    cc.nxv = c.nx / L.vec;
+    const dim3 g = step_grid(cc.nxv, c.ny, c.nz, L);
+    const int zper = check_zper(g.x, g.y, c.nz);
+    const dim3 grid(g.x, g.y, (c.nz + zper - 1) / zper), block(L.bx, L.by);
+    const size_t sh = sizeof(real) * TABW * c.nphase;
+    if (nblocks_out) *nblocks_out = grid.x * grid.y * grid.z;
+    switch (L.vec) {
+        case 4: launch_check_vec<real, 4>(cc, grid, block, sh, zper, mode, partials, q_out, (real)qscale, s); break;
+        case 2: launch_check_vec<real, 2>(cc, grid, block, sh, zper, mode, partials, q_out, (real)qscale, s); break;
+        default: launch_check_vec<real, 1>(cc, grid, block, sh, zper, mode, partials, q_out, (real)qscale, s); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double *partials, int nparts, double *final8, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partials, nparts, final8);
+    return hipGetLastError();
+}
+
+static inline int grid_1d(long long n) {
+    long long b = (n + 255) / 256;
+    return (int)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
+}
+
+template <typename real>
+hipError_t launch_init(const Cell<real> &c, real *state, const real *t0, int flags, double t_hot, double dT,
+                       hipStream_t s) {
+    hipLaunchKernelGGL((k_init<real>), dim3(grid_1d(c.N)), dim3(256), 0, s, c, state, t0, flags, t_hot, dT);
+    return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_temperature(const Cell<real> &c, const real *state, real *t_out, double t_hot, double dT,
+                              hipStream_t s) {
+    hipLaunchKernelGGL((k_temperature<real>), dim3(grid_1d(c.N)), dim3(256), 0, s, c, state, t_out, t_hot, dT);
+    return hipGetLastError();
+}
+
+hipError_t launch_phase_max(const uint8_t *phase, long long n, int *block_max, int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_phase_max, dim3(nblocks), dim3(256), 0, s, phase, n, block_max);
+    return hipGetLastError();
+}
+
+#define MRT_INST(real)                                                                                             \
+    template hipError_t launch_step<real>(const Cell<real> &, const Launch &, hipStream_t);                        \
+    template hipError_t launch_check<real>(const Cell<real> &, const Launch &, int, double *, int *, real *, double, \
+                                           hipStream_t);                                                           \
+    template int check_blocks<real>(const Cell<real> &, const Launch &);                                           \
+    template hipError_t launch_init<real>(const Cell<real> &, real *, const real *, int, double, double, hipStream_t); \
+    template hipError_t launch_temperature<real>(const Cell<real> &, const real *, real *, double, double,          \
+                                                 hipStream_t);
+MRT_INST(float)
+MRT_INST(double)
+
+}  // namespace mrt

@@ -1,0 +1,76 @@
+"""The HIP library loads and exports the C ABI (no GPU compute here)."""
+
+import ctypes
+import os
+import subprocess
+
+import pytest
+
+import paper_1503_08718_amd as pkg
+from paper_1503_08718_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libmrtlbm.so is not built (run __graft_entry__.build())")
+    return pkg.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = pkg.declared_symbols()
+    assert "mrtlbm_create" in names and "mrtlbm_batch_solve" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True, check=True)
+    exported = {l.split()[-1] for l in out.stdout.splitlines() if " T " in l}
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert getattr(lib, n) is not None
+
+
+def test_library_carries_only_gfx950_code():
+    blob = open(_lib.LIB_PATH, "rb").read()
+    import re
+
+    targets = set(re.findall(rb"amdgcn-amd-amdhsa--(gfx[0-9a-z]+)", blob))
+    assert targets == {b"gfx950"}, targets
+
+
+def test_workspace_bytes(lib):
+    f32 = lib.mrtlbm_workspace_bytes(128, 128, 128, 5, _lib.F32)
+    f64 = lib.mrtlbm_workspace_bytes(128, 128, 128, 5, _lib.F64)
+    n = 128 ** 3
+    assert f32 >= 2 * 7 * n * 4 and f64 >= 2 * 7 * n * 8
+    assert f32 < 2 * 7 * n * 4 * 1.02
+    assert lib.mrtlbm_workspace_bytes(0, 4, 4, 2, _lib.F32) == 0
+    assert lib.mrtlbm_workspace_bytes(4, 4, 4, 0, _lib.F32) == 0
+    assert lib.mrtlbm_workspace_bytes(4, 4, 4, 300, _lib.F32) == 0
+    assert lib.mrtlbm_workspace_bytes(4, 4, 4, 2, 7) == 0
+
+
+def test_errors_before_any_device_work(lib):
+    # argument checks that return before the library touches the device
+    out = ctypes.c_void_p()
+    k = (ctypes.c_double * 6)(1, 1, 1, 0, 0, 0)
+    st = lib.mrtlbm_create(4, 4, 4, None, k, 1, _lib.F32, None, 0, None, ctypes.byref(out))
+    assert st == -1 and b"NULL" in lib.mrtlbm_last_error()
+    bad = (ctypes.c_double * 6)(1, 1, 1, 2, 0, 0)  # not positive definite
+    fake = ctypes.c_void_p(256)
+    ws = lib.mrtlbm_workspace_bytes(4, 4, 4, 1, _lib.F32)
+    st = lib.mrtlbm_create(4, 4, 4, fake, bad, 1, _lib.F32, fake, ws, None, ctypes.byref(out))
+    assert st == -2
+    st = lib.mrtlbm_create(4, 4, 4, fake, k, 1, _lib.F32, fake, ws - 1, None, ctypes.byref(out))
+    assert st == -7
+    assert lib.mrtlbm_set_bc(None, 0, 1.0, 0.0, None) == -1
+    assert lib.mrtlbm_step(None, 1) == -1
+
+
+def test_product_does_not_touch_the_oracle():
+    src = os.path.join(ROOT, "paper_1503_08718_amd")
+    for dirpath, _, files in os.walk(src):
+        for fn in files:
+            if fn.endswith((".py", ".cpp", ".hip", ".h")):
+                txt = open(os.path.join(dirpath, fn)).read()
+                assert "oracle" not in txt.lower(), fn

@@ -1,0 +1,274 @@
+"""GPU (HIP, gfx950) path vs the FP64 CPU oracle, through the C ABI.
+
+Bar: FP64 fields within 1e-12 of the oracle relative to max |T| at identical
+step counts; FP64 observables within 1e-10 relative (they are sums of
+differences of O(1) numbers); FP32 within the tolerances stated per test.
+"""
+
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle import ADIABATIC, PERIODIC, TOL_KEFF, TOL_MAXDT, Oracle
+
+pytestmark = pytest.mark.gpu
+
+SIDE_NAMES = {PERIODIC: "periodic", ADIABATIC: "adiabatic"}
+
+
+@pytest.fixture(scope="module")
+def Medium():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device")
+    from paper_1503_08718_amd.solver import Medium
+
+    return Medium
+
+
+def pair(Medium, m, grad, sides, prec="f64", dmax=1.0, T0=None, launch=None, t_hot=1.0, t_cold=0.0):
+    g = Medium(m.phase, m.k, precision=prec)
+    g.set_bc(grad, t_hot, t_cold, [SIDE_NAMES[s] for s in sides])
+    if dmax != 1.0:
+        g.set_scale(dmax)
+    if launch:
+        g.set_launch(*launch)
+    g.init(T0)
+    o = Oracle(m.phase, m.k, dmax=dmax)
+    o.set_bc(grad, t_hot, t_cold, sides)
+    o.init(T0)
+    return g, o
+
+
+def field_err(g, o):
+    tg = g.temperature().double().cpu().numpy()
+    to = o.temperature()
+    return float(np.abs(tg - to).max() / max(np.abs(to).max(), 1e-300))
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+# ---------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("steps", [1, 10, 1000])
+def test_c1_field_fp64(Medium, steps):
+    m = w.c1_layered(16)
+    g, o = pair(Medium, m, 0, (0, PERIODIC, PERIODIC))
+    g.step(steps)
+    o.step(steps)
+    assert field_err(g, o) < 1e-12
+
+
+def test_c1_solve_series_mean(Medium):
+    m = w.c1_layered(16)
+    g, o = pair(Medium, m, 0, (0, PERIODIC, PERIODIC))
+    r = g.solve(1e-10, "maxdt", 200000, check_every=2)
+    assert r["converged"], r
+    exact = 14.0 / 43.0
+    for key in ("keff", "keff_hot", "keff_cold", "keff_vol"):
+        assert rel(r[key], exact) < 1e-6, (key, r)
+    # same step count on the oracle: identical field and observables
+    o.step(r["steps"])
+    assert field_err(g, o) < 1e-12
+    ko = o.keff()
+    assert rel(r["keff_hot"], ko["keff_hot"]) < 1e-10
+    assert rel(r["keff_cold"], ko["keff_cold"]) < 1e-10
+    assert rel(r["keff_vol"], ko["keff_vol"]) < 1e-10
+    assert abs(r["resid"] - ko["resid"]) < 1e-14
+
+
+CASES = [
+    # (nx, ny, nz, nphase, grad, sides, seed)
+    (12, 7, 5, 3, 0, (0, PERIODIC, ADIABATIC), 1),
+    (10, 9, 6, 4, 1, (ADIABATIC, 0, PERIODIC), 2),
+    (8, 6, 11, 3, 2, (PERIODIC, ADIABATIC, 0), 3),
+    (13, 5, 4, 2, 0, (0, ADIABATIC, ADIABATIC), 4),  # odd nx: scalar path
+    (6, 8, 7, 5, 2, (ADIABATIC, ADIABATIC, 0), 5),  # nx % 4 != 0
+    (68, 3, 3, 3, 0, (0, PERIODIC, PERIODIC), 6),  # rows longer than a wave chunk
+    (40, 4, 9, 3, 1, (PERIODIC, 0, ADIABATIC), 7),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c[:3])) + f"_g{c[4]}")
+def test_random_media_fp64(Medium, case):
+    nx, ny, nz, nph, grad, sides, seed = case
+    m = w.random_medium(seed, nx, ny, nz, nph)
+    rng = np.random.default_rng(seed)
+    T0 = rng.uniform(-0.5, 1.5, m.phase.shape)
+    g, o = pair(Medium, m, grad, sides, T0=T0, t_hot=0.8, t_cold=-0.4)
+    for n in (1, 7, 60):
+        g.step(n)
+        o.step(n)
+        assert field_err(g, o) < 1e-12, n
+    # observables of the next transition: GPU probe at t vs oracle at t+1
+    kg = g.keff()
+    o.step(1)
+    ko = o.keff()
+    for key in ("keff_hot", "keff_cold", "keff_vol"):
+        assert abs(kg[key] - ko[key]) < 1e-10 * max(1.0, abs(ko[key])), key
+    assert np.allclose(kg["keff_col"], ko["keff_col"], rtol=1e-10, atol=1e-10)
+    assert abs(kg["resid"] - ko["resid"]) < 1e-13
+
+
+def test_flux_field_fp64(Medium):
+    m = w.random_medium(8, 12, 6, 5, 3)
+    rng = np.random.default_rng(8)
+    T0 = rng.uniform(0, 1, m.phase.shape)
+    g, o = pair(Medium, m, 0, (0, ADIABATIC, PERIODIC), T0=T0)
+    g.step(25)
+    o.step(26)
+    qg = g.flux().cpu().numpy()
+    qo, _ = o.flux()
+    qo = qo / o.scale  # oracle flux is in lattice units
+    assert np.abs(qg - qo).max() < 1e-11 * np.abs(qo).max()
+
+
+@pytest.mark.parametrize("launch", [(1, 16, 4), (2, 8, 8), (2, 32, 2), (4, 8, 16), (4, 64, 1), (1, 64, 4)])
+def test_launch_shapes_bitwise_identical(Medium, launch):
+    m = w.random_medium(9, 32, 12, 6, 3)
+    ref, _ = pair(Medium, m, 1, (ADIABATIC, 0, PERIODIC))
+    ref.step(40)
+    g, _ = pair(Medium, m, 1, (ADIABATIC, 0, PERIODIC), launch=launch)
+    g.step(40)
+    import torch
+
+    assert torch.equal(ref.state_get(), g.state_get())
+    assert ref.keff() == g.keff() or abs(ref.keff()["keff_hot"] - g.keff()["keff_hot"]) < 1e-15
+
+
+def test_checkpoint_resume_bitwise(Medium):
+    import torch
+
+    m = w.braid(16, 16, 24, 30.0, 0.5)
+    for prec in ("f32", "f64"):
+        a = Medium(m.phase, m.k, precision=prec).set_bc(2).init()
+        a.step(50)
+        snap = a.state_get().clone()
+        a.step(70)
+        b = Medium(m.phase, m.k, precision=prec).set_bc(2)
+        b.state_set(snap, steps=50)
+        b.step(70)
+        assert torch.equal(a.state_get(), b.state_get())
+        assert a.info()["steps"] == b.info()["steps"] == 120
+
+
+def test_determinism_of_solve(Medium):
+    m = w.braid(24, 24, 24, 35.0, 0.45)
+    out = []
+    for _ in range(2):
+        g = Medium(m.phase, m.k, precision="f32").set_bc(0).init()
+        out.append(g.solve(1e-3, "keff", 40000, check_every=200))
+    assert out[0] == out[1]
+
+
+def test_warm_start_init_matches_oracle(Medium):
+    m = w.random_medium(10, 9, 8, 7, 3)
+    rng = np.random.default_rng(10)
+    T0 = rng.uniform(0, 1, m.phase.shape)
+    g, o = pair(Medium, m, 2, (PERIODIC, ADIABATIC, 0), T0=T0)
+    assert field_err(g, o) < 1e-14
+    g.step(33)
+    o.step(33)
+    assert field_err(g, o) < 1e-12
+
+
+def test_fp32_close_to_fp64(Medium):
+    m = w.braid(32, 32, 32, 30.0, 0.5)
+    res = {}
+    for prec in ("f32", "f64"):
+        g = Medium(m.phase, m.k, precision=prec).set_bc(0).init()
+        res[prec] = g.solve(1e-6, "keff", 2_000_000, check_every=500)
+        assert res[prec]["converged"]
+    assert rel(res["f32"]["keff"], res["f64"]["keff"]) < 1e-4
+
+
+# ---------------------------------------------------------------------------
+# full-size windows: the configurations the benchmark times
+# ---------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("n,prec,tol", [(128, "f64", 1e-12), (128, "f32", 2e-6)])
+def test_braid_window_full_size(Medium, n, prec, tol):
+    m = w.braid(n, n, n, 30.0, 0.5)
+    rng = np.random.default_rng(128)
+    # smooth random start so that every node is active from the first step
+    z, y, x = np.meshgrid(*(np.linspace(0, 2 * np.pi, n, endpoint=False),) * 3, indexing="ij")
+    T0 = 0.5 + 0.3 * np.sin(x + rng.uniform(0, 6)) * np.cos(2 * y) + 0.1 * np.sin(3 * z)
+    g, o = pair(Medium, m, 0, (0, PERIODIC, PERIODIC), prec=prec, T0=T0)
+    o.set_threads(0)
+    steps = 12
+    g.step(steps)
+    o.step(steps)
+    assert field_err(g, o) < tol
+    kg = g.keff()
+    o.step(1)
+    ko = o.keff()
+    ktol = 1e-9 if prec == "f64" else 2e-3
+    assert abs(kg["keff_vol"] - ko["keff_vol"]) < ktol * abs(ko["keff_vol"])
+
+
+def test_energy_identity_full_size(Medium):
+    # sum T(t+1) - sum T(t) = Phi_hot - Phi_cold (collision conserves T,
+    # interior / periodic / adiabatic links conserve the sum)
+    n = 128
+    m = w.braid(n, n, n, 30.0, 0.5)
+    g = Medium(m.phase, m.k, precision="f64").set_bc(2, sides=("periodic", "adiabatic", "periodic")).init()
+    g.step(200)
+    t0 = g.temperature().sum().item()
+    k = g.keff()
+    g.step(1)
+    t1 = g.temperature().sum().item()
+    info = g.info()
+    area = n * n
+    ng = n
+    s = info["scale"]
+    phi_hot = k["keff_hot"] * area * s / ng
+    phi_cold = k["keff_cold"] * area * s / ng
+    assert abs((t1 - t0) - (phi_hot - phi_cold)) < 1e-9 * max(1.0, abs(phi_hot))
+
+
+# ---------------------------------------------------------------------------
+# error paths
+# ---------------------------------------------------------------------------
+
+
+def test_rejects_bad_phase_and_tensor(Medium):
+    from paper_1503_08718_amd import MrtlbmError
+
+    m = w.random_medium(11, 4, 4, 4, 2)
+    ph = m.phase.copy()
+    ph[1, 2, 3] = 5
+    with pytest.raises(MrtlbmError, match="E_ARG"):
+        Medium(ph, m.k)
+    bad = m.k.copy()
+    bad[0] = [1, 1, 1, 2, 0, 0]
+    with pytest.raises(MrtlbmError, match="E_TENSOR"):
+        Medium(m.phase, bad)
+    g = Medium(m.phase, m.k)
+    with pytest.raises(MrtlbmError, match="E_BC"):
+        g.set_bc(3)
+    with pytest.raises(MrtlbmError, match="E_ARG"):
+        g.step(1)  # not initialised
+
+
+def test_nonfinite_start_is_reported(Medium):
+    from paper_1503_08718_amd import MrtlbmError
+
+    m = w.random_medium(12, 8, 8, 8, 2)
+    T0 = np.zeros(m.phase.shape)
+    T0[3, 3, 3] = np.nan
+    g = Medium(m.phase, m.k, precision="f32").set_bc(0).init(T0)
+    with pytest.raises(MrtlbmError, match="E_NONFINITE"):
+        g.solve(1e-6, "keff", 1000, check_every=10)
+
+
+def test_max_steps_gives_partial_result(Medium):
+    m = w.braid(16, 16, 16, 30.0, 0.5)
+    g = Medium(m.phase, m.k).set_bc(0).init()
+    r = g.solve(1e-9, "keff", 300, check_every=100)
+    assert r["status"] == "NOT_CONVERGED" and not r["converged"] and r["steps"] == 300
+    assert r["keff_hot"] > r["keff_cold"]
