@@ -1,8 +1,228 @@
-// placeholder, replaced by the batched driver
+// Batched many-cell driver: all still-active cells advance together, one
+// kernel launch per step over a table of row tiles, the steps between two
+// checks replayed as one hip graph; a cell leaves the table when its own stop
+// rule holds (the same rule as mrtlbm_solve).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "batch_internal.h"
 #include "medium.h"
+
 using namespace mrt;
-extern "C" size_t mrtlbm_batch_workspace_bytes(mrtlbm_medium *const *, int) { return 0; }
-extern "C" mrtlbm_status mrtlbm_batch_solve(mrtlbm_medium *const *, int, double, mrtlbm_tol_kind, long long, int,
-                                            void *, size_t, mrtlbm_result *) {
-    return fail(MRTLBM_E_ARG, "not built");
+
+namespace {
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct BatchLayout {
+    size_t cells, tiles, partials, start, finals, total;
+    long long max_tiles;
+};
+
+bool batch_layout(mrtlbm_medium *const *cells, int n, BatchLayout *L) {
+    if (!cells || n < 1) return false;
+    long long mt = 0;
+    for (int i = 0; i < n; i++) {
+        if (!cells[i]) return false;
+        mt += (long long)cells[i]->nz * cells[i]->ny;
+    }
+    if (mt > (1LL << 31) - 1) return false;
+    size_t o = 0;
+    L->cells = o; o = align256(o + (size_t)n * sizeof(Cell<double>));
+    L->tiles = o; o = align256(o + (size_t)mt * sizeof(int4));
+    L->partials = o; o = align256(o + (size_t)mt * NRED * sizeof(double));
+    L->start = o; o = align256(o + (size_t)(n + 1) * sizeof(int));
+    L->finals = o; o = align256(o + (size_t)n * NRED * sizeof(double));
+    L->total = o;
+    L->max_tiles = mt;
+    return true;
+}
+
+struct BatchRun {
+    mrtlbm_medium *const *cells;
+    int n;
+    int vec, threads, max_nphase;
+    char *ws;
+    BatchLayout lay;
+    hipStream_t stream, cap;
+    double *pinned = nullptr;
+    std::vector<int> active;  // indices into cells
+    int ntiles = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    ~BatchRun() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap) (void)hipStreamDestroy(cap);
+        if (pinned) (void)hipHostFree(pinned);
+    }
+};
+
+template <typename real>
+mrtlbm_status upload_cells(BatchRun &B) {
+    std::vector<Cell<real>> desc(B.n);
+    for (int i = 0; i < B.n; i++) {
+        desc[i] = make_cell<real>(B.cells[i], B.cells[i]->cur);
+        desc[i].nxv = B.cells[i]->nx / B.vec;
+    }
+    hipError_t e = hipMemcpyAsync(B.ws + B.lay.cells, desc.data(), desc.size() * sizeof(Cell<real>),
+                                  hipMemcpyHostToDevice, B.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(B.stream);
+    return e == hipSuccess ? MRTLBM_OK : hip_fail(e, "batch cell table upload");
+}
+
+// tiles of the active cells (contiguous per cell) and per-cell tile ranges
+mrtlbm_status upload_tiles(BatchRun &B) {
+    std::vector<int4> tiles;
+    std::vector<int> start;
+    for (int a : B.active) {
+        const mrtlbm_medium *m = B.cells[a];
+        const int nxv = m->nx / B.vec;
+        const int rows = B.threads / nxv;
+        start.push_back((int)tiles.size());
+        for (int z = 0; z < m->nz; z++)
+            for (int y0 = 0; y0 < m->ny; y0 += rows) tiles.push_back(int4{a, z, y0, std::min(rows, m->ny - y0)});
+    }
+    start.push_back((int)tiles.size());
+    B.ntiles = (int)tiles.size();
+    if ((long long)B.ntiles > B.lay.max_tiles) return fail(MRTLBM_E_WORKSPACE, "tile table overflow");
+    hipError_t e = hipMemcpyAsync(B.ws + B.lay.tiles, tiles.data(), tiles.size() * sizeof(int4), hipMemcpyHostToDevice,
+                                  B.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(B.ws + B.lay.start, start.data(), start.size() * sizeof(int), hipMemcpyHostToDevice, B.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(B.stream);
+    return e == hipSuccess ? MRTLBM_OK : hip_fail(e, "batch tile table upload");
+}
+
+template <typename real>
+mrtlbm_status build_graph(BatchRun &B, int K) {
+    if (B.exec) { (void)hipGraphExecDestroy(B.exec); B.exec = nullptr; }
+    if (B.graph) { (void)hipGraphDestroy(B.graph); B.graph = nullptr; }
+    const Cell<real> *cells = (const Cell<real> *)(B.ws + B.lay.cells);
+    const int4 *tiles = (const int4 *)(B.ws + B.lay.tiles);
+    double *partials = (double *)(B.ws + B.lay.partials);
+    const int *start = (const int *)(B.ws + B.lay.start);
+    double *finals = (double *)(B.ws + B.lay.finals);
+    hipError_t e = hipStreamBeginCapture(B.cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    for (int i = 0; i < K && e == hipSuccess; i++)
+        e = launch_batch<real>(cells, tiles, B.ntiles, B.vec, B.threads, B.max_nphase, i & 1, i == K - 1, partials,
+                               B.cap);
+    if (e == hipSuccess) e = launch_batch_reduce(partials, start, (int)B.active.size(), finals, B.cap);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(B.pinned, finals, B.active.size() * NRED * sizeof(double), hipMemcpyDeviceToHost, B.cap);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(B.cap, &g);
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(e, "batch graph capture");
+    }
+    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+    B.graph = g;
+    e = hipGraphInstantiate(&B.exec, g, nullptr, nullptr, 0);
+    return e == hipSuccess ? MRTLBM_OK : hip_fail(e, "batch graph instantiate");
+}
+
+template <typename real>
+mrtlbm_status run(BatchRun &B, double tol, mrtlbm_tol_kind kind, long long max_steps, int K, mrtlbm_result *out) {
+    mrtlbm_status st = upload_cells<real>(B);
+    if (st != MRTLBM_OK) return st;
+    std::vector<StopState> ss(B.n);
+    std::vector<int> state(B.n, 0);  // 0 active, 1 converged, 2 out of steps, -1 non-finite, -2 diverged
+    for (int i = 0; i < B.n; i++) {
+        std::vector<double> zero(NRED, 0.0);
+        fill_result(B.cells[i], zero.data(), &out[i]);
+        if (B.cells[i]->steps + K <= max_steps) B.active.push_back(i);
+        else state[i] = 2;
+    }
+    bool rebuild = true;
+    while (!B.active.empty()) {
+        if (rebuild) {
+            st = upload_tiles(B);
+            if (st == MRTLBM_OK) st = build_graph<real>(B, K);
+            if (st != MRTLBM_OK) return st;
+            rebuild = false;
+        }
+        hipError_t e = hipGraphLaunch(B.exec, B.stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(B.stream);
+        if (e != hipSuccess) return hip_fail(e, "batch graph launch");
+        std::vector<int> still;
+        for (size_t k = 0; k < B.active.size(); k++) {
+            const int i = B.active[k];
+            mrtlbm_medium *m = B.cells[i];
+            m->steps += K;
+            fill_result(m, B.pinned + k * NRED, &out[i]);
+            const int v = stop_rule(ss[i], out[i], tol, kind);
+            if (v == 1) { out[i].converged = 1; state[i] = 1; }
+            else if (v < 0) state[i] = v;
+            else if (m->steps + K > max_steps) state[i] = 2;
+            else still.push_back(i);
+        }
+        if (still.size() != B.active.size()) rebuild = true;
+        B.active.swap(still);
+    }
+    int worst = 0;
+    for (int i = 0; i < B.n; i++) {
+        if (state[i] == -1) return fail(MRTLBM_E_NONFINITE, "cell %d became non-finite", i);
+        if (state[i] == -2) worst = -2;
+        if (state[i] == 2 && worst == 0) worst = 2;
+    }
+    if (worst == -2) return fail(MRTLBM_E_DIVERGED, "a cell diverged");
+    return worst == 2 ? MRTLBM_NOT_CONVERGED : MRTLBM_OK;
+}
+
+}  // namespace
+
+extern "C" size_t mrtlbm_batch_workspace_bytes(mrtlbm_medium *const *cells, int n) {
+    BatchLayout L;
+    return batch_layout(cells, n, &L) ? L.total : 0;
+}
+
+extern "C" mrtlbm_status mrtlbm_batch_solve(mrtlbm_medium *const *cells, int n, double tol, mrtlbm_tol_kind kind,
+                                            long long max_steps, int check_every, void *workspace_dev,
+                                            size_t workspace_bytes, mrtlbm_result *out) {
+    BatchLayout lay;
+    if (!out || !batch_layout(cells, n, &lay)) return fail(MRTLBM_E_ARG, "bad cell list");
+    if (!workspace_dev || workspace_bytes < lay.total)
+        return fail(MRTLBM_E_WORKSPACE, "batch workspace of %zu bytes, need %zu", workspace_bytes, lay.total);
+    if (((uintptr_t)workspace_dev) & 255) return fail(MRTLBM_E_WORKSPACE, "workspace not 256-byte aligned");
+    if (check_every < 2 || (check_every & 1)) return fail(MRTLBM_E_ARG, "check_every must be even and >= 2");
+    if (!(tol > 0)) return fail(MRTLBM_E_ARG, "tol must be > 0");
+    if (kind != MRTLBM_TOL_MAXDT && kind != MRTLBM_TOL_KEFF) return fail(MRTLBM_E_ARG, "bad tolerance kind");
+    const mrtlbm_medium *m0 = cells[0];
+    int vec = m0->launch.vec, threads = m0->launch.bx * m0->launch.by, max_nphase = 1;
+    for (int i = 0; i < n; i++) {
+        const mrtlbm_medium *m = cells[i];
+        if (!m->initialised) return fail(MRTLBM_E_ARG, "cell %d is not initialised", i);
+        if (m->prec != m0->prec) return fail(MRTLBM_E_ARG, "cells mix precisions");
+        if (m->stream != m0->stream || m->device != m0->device) return fail(MRTLBM_E_ARG, "cells mix streams/devices");
+        while (m->nx % vec) vec >>= 1;
+        max_nphase = std::max(max_nphase, m->nphase);
+        for (int j = 0; j < i; j++)
+            if (cells[j] == m) return fail(MRTLBM_E_ARG, "cell %d listed twice", i);
+    }
+    if (vec < 1) vec = 1;
+    for (int i = 0; i < n; i++)
+        if (cells[i]->nx / vec > threads) threads = 256;
+    for (int i = 0; i < n; i++)
+        if (cells[i]->nx / vec > threads) return fail(MRTLBM_E_ARG, "cell %d: rows of %d nodes are too long to batch", i, cells[i]->nx);
+    BatchRun B;
+    B.cells = cells;
+    B.n = n;
+    B.vec = vec;
+    B.threads = threads;
+    B.max_nphase = max_nphase;
+    B.ws = (char *)workspace_dev;
+    B.lay = lay;
+    B.stream = m0->stream;
+    B.cap = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&B.cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&B.pinned, (size_t)n * NRED * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(e, "batch setup");
+    return m0->prec == MRTLBM_F64 ? run<double>(B, tol, kind, max_steps, check_every, out)
+                                  : run<float>(B, tol, kind, max_steps, check_every, out);
 }

@@ -177,13 +177,16 @@ def test_warm_start_init_matches_oracle(Medium):
 
 
 def test_fp32_close_to_fp64(Medium):
+    # FP32 at the production tolerance (wall-flux gap 1e-4) against an FP64
+    # solve converged far tighter
     m = w.braid(32, 32, 32, 30.0, 0.5)
-    res = {}
-    for prec in ("f32", "f64"):
-        g = Medium(m.phase, m.k, precision=prec).set_bc(0).init()
-        res[prec] = g.solve(1e-6, "keff", 2_000_000, check_every=500)
-        assert res[prec]["converged"]
-    assert rel(res["f32"]["keff"], res["f64"]["keff"]) < 1e-4
+    g64 = Medium(m.phase, m.k, precision="f64").set_bc(0).init()
+    r64 = g64.solve(1e-9, "keff", 2_000_000, check_every=500)
+    assert r64["converged"], r64
+    g32 = Medium(m.phase, m.k, precision="f32").set_bc(0).init()
+    r32 = g32.solve(1e-4, "keff", 2_000_000, check_every=500)
+    assert r32["converged"], r32
+    assert rel(r32["keff"], r64["keff"]) < 1e-4
 
 
 # ---------------------------------------------------------------------------
