@@ -81,7 +81,7 @@ def main():
     g = Medium(m.phase, m.k, precision=prec, device="cuda:0")
     g.set_bc(0, 1.0, 0.0, ("periodic", "periodic", "periodic"))
     if args.launch:
-        g.set_launch(*[int(v) for v in args.launch.split(",")])
+        g.set_launch(*[int(v) for v in args.launch.split(",")])  # vec,bx,by[,nt]
     elif os.path.exists(args.tune_cache):
         g.load_tuned(args.tune_cache)
     g.init()
@@ -120,7 +120,7 @@ def main():
                         f"k_axial 10 / k_trans 1 / matrix 0.2, x gradient, periodic sides, {prec.upper()}",
             "nodes": nodes,
             "check_every": K,
-            "launch": list(g.info()["launch"]),
+            "launch": dict(zip(("vec", "bx", "by", "nt"), g.info()["launch"])),
         },
         "roofline": {
             "bound": "hbm",

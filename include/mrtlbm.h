@@ -51,7 +51,7 @@ typedef enum { MRTLBM_F32 = 0, MRTLBM_F64 = 1 } mrtlbm_precision;
 typedef enum { MRTLBM_PERIODIC = 0, MRTLBM_ADIABATIC = 1 } mrtlbm_side;
 typedef enum {
     MRTLBM_TOL_MAXDT = 0, /* stop when max |T(t) - T(t-1)| at a check < tol                        */
-    MRTLBM_TOL_KEFF = 1   /* stop when |k_hot - k_cold| / k_mid < tol and k_mid moved < tol/10     */
+    MRTLBM_TOL_KEFF = 1   /* stop when |k_hot - k_cold + k_leak| / k_mid < tol and k_mid moved < tol/10 */
 } mrtlbm_tol_kind;
 
 typedef struct mrtlbm_medium mrtlbm_medium;
@@ -66,13 +66,19 @@ typedef struct mrtlbm_medium mrtlbm_medium;
  *   keff_col[a] = N_g <q_a> / (dT s): the gradient column of the effective
  *       tensor (keff_col[grad_axis] == keff_vol);
  *   resid = max over nodes of |T(t+1) - T(t)|;
- *   temp_mean = mean T(t+1).
+ *   temp_mean = mean T(t+1);
+ *   keff_leak = N_g L / (dT A s), L the energy the rounding of this step
+ *       added to the stored state (summed exactly in FP64); at steady state
+ *       keff_hot - keff_cold + keff_leak = 0, and the MRTLBM_TOL_KEFF rule
+ *       tests |keff_hot - keff_cold + keff_leak| / keff (the stored energy's
+ *       rate of change), which equals the wall-flux gap in exact arithmetic.
  */
 typedef struct {
     double keff, keff_hot, keff_cold, keff_vol;
     double keff_col[3];
     double resid;
     double temp_mean;
+    double keff_leak;
     long long steps;  /* steps taken by the medium when the values were taken */
     int converged;
     int nonfinite;    /* nodes whose T(t+1) is not finite */
@@ -81,8 +87,10 @@ typedef struct {
 /* Thread-block shape of the step kernel: each thread updates `vec`
  * consecutive x nodes; a block is bx x by threads over (x-vectors, rows).
  * vec in {1, 2, 4} (nx % vec == 0), bx in {8, 16, 32, 64}, bx*by in [64, 256]
- * and a multiple of 64, vec*bx >= 16. */
-typedef struct { int vec, bx, by; } mrtlbm_launch;
+ * and a multiple of 64, vec*bx >= 16.  nt: cache policy of the state
+ * streams, bit 0 = non-temporal loads, bit 1 = non-temporal stores.
+ * The batched solver uses vec and bx*by (threads per row tile) of cells[0]. */
+typedef struct { int vec, bx, by, nt; } mrtlbm_launch;
 
 /* Bytes of caller-owned device workspace a medium of these sizes needs
  * (two state buffers of 7 reals per node, reduction partials and tables),

@@ -33,6 +33,7 @@ class Result(ctypes.Structure):
         ("keff_col", ctypes.c_double * 3),
         ("resid", ctypes.c_double),
         ("temp_mean", ctypes.c_double),
+        ("keff_leak", ctypes.c_double),
         ("steps", ctypes.c_longlong),
         ("converged", ctypes.c_int),
         ("nonfinite", ctypes.c_int),
@@ -40,12 +41,13 @@ class Result(ctypes.Structure):
 
     def to_dict(self) -> dict:
         return dict(keff=self.keff, keff_hot=self.keff_hot, keff_cold=self.keff_cold, keff_vol=self.keff_vol,
-                    keff_col=list(self.keff_col), resid=self.resid, temp_mean=self.temp_mean, steps=self.steps,
+                    keff_col=list(self.keff_col), resid=self.resid, temp_mean=self.temp_mean,
+                    keff_leak=self.keff_leak, steps=self.steps,
                     converged=bool(self.converged), nonfinite=self.nonfinite)
 
 
 class Launch(ctypes.Structure):
-    _fields_ = [("vec", ctypes.c_int), ("bx", ctypes.c_int), ("by", ctypes.c_int)]
+    _fields_ = [("vec", ctypes.c_int), ("bx", ctypes.c_int), ("by", ctypes.c_int), ("nt", ctypes.c_int)]
 
 
 _lib = None

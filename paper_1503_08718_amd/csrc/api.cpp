@@ -147,6 +147,7 @@ bool mrt::launch_ok(const mrtlbm_medium *m, const Launch &L) {
     const int t = L.bx * L.by;
     if (L.by < 1 || t < 64 || t > 256 || (t % 64)) return false;
     if (L.vec * L.bx < 16) return false;
+    if (L.nt < 0 || L.nt > 3) return false;
     return true;
 }
 
@@ -160,6 +161,7 @@ Launch mrt::default_launch(const mrtlbm_medium *m) {
     while (L.vec * bx < 16) bx *= 2;
     L.bx = bx;
     L.by = 256 / bx;
+    L.nt = 0;
     return L;
 }
 
@@ -353,15 +355,18 @@ extern "C" mrtlbm_status mrtlbm_info(const mrtlbm_medium *m, double *scale, long
     if (!m) return fail(MRTLBM_E_ARG, "medium is NULL");
     if (scale) *scale = m->s;
     if (steps) *steps = m->steps;
-    if (launch) { launch->vec = m->launch.vec; launch->bx = m->launch.bx; launch->by = m->launch.by; }
+    if (launch) {
+        launch->vec = m->launch.vec; launch->bx = m->launch.bx; launch->by = m->launch.by; launch->nt = m->launch.nt;
+    }
     return MRTLBM_OK;
 }
 
 extern "C" mrtlbm_status mrtlbm_set_launch(mrtlbm_medium *m, const mrtlbm_launch *launch) {
     if (!m) return fail(MRTLBM_E_ARG, "medium is NULL");
-    Launch L = launch ? Launch{launch->vec, launch->bx, launch->by} : default_launch(m);
-    if (!launch_ok(m, L)) return fail(MRTLBM_E_ARG, "launch shape vec=%d bx=%d by=%d not admissible", L.vec, L.bx, L.by);
-    if (L.vec != m->launch.vec || L.bx != m->launch.bx || L.by != m->launch.by) drop_graphs(m);
+    Launch L = launch ? Launch{launch->vec, launch->bx, launch->by, launch->nt} : default_launch(m);
+    if (!launch_ok(m, L))
+        return fail(MRTLBM_E_ARG, "launch shape vec=%d bx=%d by=%d nt=%d not admissible", L.vec, L.bx, L.by, L.nt);
+    drop_graphs(m);
     m->launch = L;
     return MRTLBM_OK;
 }
@@ -488,6 +493,7 @@ void mrt::fill_result(const mrtlbm_medium *m, const double *f, mrtlbm_result *ou
     out->resid = f[R_RESID];
     out->temp_mean = f[R_TSUM] / (double)m->N + 0.5 * (m->t_hot + m->t_cold);
     out->nonfinite = (int)f[R_NONFINITE];
+    out->keff_leak = ng * f[R_LEAK] / (dT * area * s);
     out->steps = m->steps;
     out->converged = 0;
 }
@@ -534,8 +540,11 @@ int mrt::stop_rule(StopState &ss, const mrtlbm_result &r, double tol, mrtlbm_tol
     if (ss.min_resid > 0 && r.resid > 1e3 * ss.min_resid && r.resid > 1e-6) return -2;
     if (ss.min_resid < 0 || r.resid < ss.min_resid) ss.min_resid = r.resid;
     if (kind == MRTLBM_TOL_MAXDT) return r.resid < tol ? 1 : 0;
+    // energy accumulation rate through the walls plus the exact rounding
+    // energy of the stored state: dE/dt of the stored field, relative to the
+    // through-flux (equal to the plain wall-flux gap in exact arithmetic)
     const double km = r.keff;
-    const bool gap_ok = std::fabs(r.keff_hot - r.keff_cold) < tol * std::fabs(km);
+    const bool gap_ok = std::fabs(r.keff_hot - r.keff_cold + r.keff_leak) < tol * std::fabs(km);
     const bool chg_ok = ss.have_prev && std::fabs(km - ss.kprev) < 0.1 * tol * std::fabs(km);
     ss.kprev = km;
     ss.have_prev = true;
@@ -651,7 +660,7 @@ extern "C" mrtlbm_status mrtlbm_autotune(mrtlbm_medium *m, const char *cache_pat
     mrtlbm_status st = mrtlbm_init(m, nullptr, 0);
     if (st != MRTLBM_OK) return st;
     const double bytes_per_step = (double)m->N * (m->prec == MRTLBM_F64 ? 113.0 : 57.0);
-    long long n = (long long)std::ceil(4e9 / bytes_per_step);
+    long long n = (long long)std::ceil(2e10 / bytes_per_step);
     n = std::max(4LL, std::min(n, 2000LL));
     n += (n & 1);
     Launch bestL = m->launch;
@@ -659,8 +668,9 @@ extern "C" mrtlbm_status mrtlbm_autotune(mrtlbm_medium *m, const char *cache_pat
     const Launch saved = m->launch;
     for (int vec : {4, 2, 1})
         for (int bx : {8, 16, 32, 64})
-            for (int t : {64, 128, 256}) {
-                Launch L{vec, bx, t / bx};
+            for (int t : {64, 128, 256})
+                for (int nt : {0, 1, 2, 3}) {
+                Launch L{vec, bx, t / bx, nt};
                 if (t % bx || !launch_ok(m, L)) continue;
                 if (L.bx > 2 * std::max(8, m->nx / vec)) continue;  // mostly idle lanes
                 m->launch = L;
@@ -680,7 +690,7 @@ extern "C" mrtlbm_status mrtlbm_autotune(mrtlbm_medium *m, const char *cache_pat
     m->launch = bestL;
     drop_graphs(m);
     m->initialised = false;
-    if (best) { best->vec = bestL.vec; best->bx = bestL.bx; best->by = bestL.by; }
+    if (best) { best->vec = bestL.vec; best->bx = bestL.bx; best->by = bestL.by; best->nt = bestL.nt; }
     if (cache_path) {
         const std::string key = tune_key(m);
         std::vector<std::string> lines;
@@ -691,7 +701,7 @@ extern "C" mrtlbm_status mrtlbm_autotune(mrtlbm_medium *m, const char *cache_pat
                 if (line.compare(0, key.size() + 1, key + " ") != 0 && !line.empty()) lines.push_back(line);
         }
         std::ostringstream l;
-        l << key << ' ' << bestL.vec << ' ' << bestL.bx << ' ' << bestL.by << ' ' << (bestms / n);
+        l << key << ' ' << bestL.vec << ' ' << bestL.bx << ' ' << bestL.by << ' ' << bestL.nt << ' ' << (bestms / n);
         lines.push_back(l.str());
         std::ofstream o(cache_path, std::ios::trunc);
         for (auto &s : lines) o << s << '\n';
@@ -709,8 +719,8 @@ extern "C" mrtlbm_status mrtlbm_load_tuned(mrtlbm_medium *m, const char *cache_p
         if (line.compare(0, key.size() + 1, key + " ") != 0) continue;
         std::istringstream r(line.substr(key.size() + 1));
         Launch L{};
-        if (r >> L.vec >> L.bx >> L.by && launch_ok(m, L)) {
-            if (L.vec != m->launch.vec || L.bx != m->launch.bx || L.by != m->launch.by) drop_graphs(m);
+        if (r >> L.vec >> L.bx >> L.by >> L.nt && launch_ok(m, L)) {
+            drop_graphs(m);
             m->launch = L;
             return MRTLBM_OK;
         }

@@ -17,30 +17,33 @@ struct Vec {
     real v[VEC];
 };
 
-template <typename real, int VEC>
+// NT: streaming (non-temporal) cache policy for the state loads / stores.
+template <typename real, int VEC, bool NT = false>
 __device__ __forceinline__ Vec<real, VEC> vload(const real *__restrict__ p) {
     Vec<real, VEC> r;
     if constexpr (VEC == 1) {
-        r.v[0] = p[0];
+        r.v[0] = NT ? __builtin_nontemporal_load(p) : p[0];
     } else {
         typedef real vt __attribute__((ext_vector_type(VEC)));
-        vt t = *reinterpret_cast<const vt *>(p);
+        vt t = NT ? __builtin_nontemporal_load(reinterpret_cast<const vt *>(p)) : *reinterpret_cast<const vt *>(p);
 #pragma unroll
         for (int i = 0; i < VEC; i++) r.v[i] = t[i];
     }
     return r;
 }
 
-template <typename real, int VEC>
+template <typename real, int VEC, bool NT = false>
 __device__ __forceinline__ void vstore(real *__restrict__ p, const Vec<real, VEC> &r) {
     if constexpr (VEC == 1) {
-        p[0] = r.v[0];
+        if constexpr (NT) __builtin_nontemporal_store(r.v[0], p);
+        else p[0] = r.v[0];
     } else {
         typedef real vt __attribute__((ext_vector_type(VEC)));
         vt t;
 #pragma unroll
         for (int i = 0; i < VEC; i++) t[i] = r.v[i];
-        *reinterpret_cast<vt *>(p) = t;
+        if constexpr (NT) __builtin_nontemporal_store(t, reinterpret_cast<vt *>(p));
+        else *reinterpret_cast<vt *>(p) = t;
     }
 }
 
@@ -76,8 +79,9 @@ struct XLink {
     bool haveL, haveR;
 };
 
-// MODE 0: step; 1: step + observables; 2: observables only; 3: as 2 + flux field
-template <typename real, int VEC, int MODE>
+// MODE 0: step; 1: step + observables; 2: observables only; 3: as 2 + flux field.
+// NT bit 0: non-temporal state loads; bit 1: non-temporal state stores.
+template <typename real, int VEC, int MODE, int NT = 0>
 __device__ __forceinline__ void node_update(const Cell<real> &c, const real *__restrict__ tab, int xv, int y, int z,
                                             bool active, const XLink &xl, Acc &acc, real *__restrict__ qout,
                                             real qscale) {
@@ -98,13 +102,13 @@ __device__ __forceinline__ void node_update(const Cell<real> &c, const real *__r
     if (zlo) { if (c.per[2]) zm = nz - 1; else { zm = z; pzm = 6; } }
     if (zhi) { if (c.per[2]) zp = 0; else { zp = z; pzp = 5; } }
 
-    Vec<real, VEC> c0 = vload<real, VEC>(s + base);
-    Vec<real, VEC> a1 = vload<real, VEC>(s + N + base);
-    Vec<real, VEC> a2 = vload<real, VEC>(s + 2 * N + base);
-    Vec<real, VEC> b3 = vload<real, VEC>(s + pym * N + ((long long)z * ny + ym) * nx + x0);
-    Vec<real, VEC> b4 = vload<real, VEC>(s + pyp * N + ((long long)z * ny + yp) * nx + x0);
-    Vec<real, VEC> b5 = vload<real, VEC>(s + pzm * N + ((long long)zm * ny + y) * nx + x0);
-    Vec<real, VEC> b6 = vload<real, VEC>(s + pzp * N + ((long long)zp * ny + y) * nx + x0);
+    Vec<real, VEC> c0 = vload<real, VEC, (NT & 1) != 0>(s + base);
+    Vec<real, VEC> a1 = vload<real, VEC, (NT & 1) != 0>(s + N + base);
+    Vec<real, VEC> a2 = vload<real, VEC, (NT & 1) != 0>(s + 2 * N + base);
+    Vec<real, VEC> b3 = vload<real, VEC, (NT & 1) != 0>(s + pym * N + ((long long)z * ny + ym) * nx + x0);
+    Vec<real, VEC> b4 = vload<real, VEC, (NT & 1) != 0>(s + pyp * N + ((long long)z * ny + yp) * nx + x0);
+    Vec<real, VEC> b5 = vload<real, VEC, (NT & 1) != 0>(s + pzm * N + ((long long)zm * ny + y) * nx + x0);
+    Vec<real, VEC> b6 = vload<real, VEC, (NT & 1) != 0>(s + pzp * N + ((long long)zp * ny + y) * nx + x0);
     int ph[VEC];
     load_phase<VEC>(c.phase + base, ph);
     Vec<real, VEC> o3, o4, o5, o6;
@@ -143,12 +147,13 @@ __device__ __forceinline__ void node_update(const Cell<real> &c, const real *__r
 #pragma unroll
     for (int v = 0; v < VEC; v++) {
         const real f0 = c0.v[v];
-        const real f1 = (v == 0 ? left : a1.v[v - 1]) + hx;
-        const real f2 = (v == VEC - 1 ? right : a2.v[v + 1]) - hx;
-        const real f3 = sy3 * b3.v[v] + hy;
-        const real f4 = sy4 * b4.v[v] - hy;
-        const real f5 = sz5 * b5.v[v] + hz;
-        const real f6 = sz6 * b6.v[v] - hz;
+        const real r1 = (v == 0 ? left : a1.v[v - 1]);
+        const real r2 = (v == VEC - 1 ? right : a2.v[v + 1]);
+        const real r3 = sy3 * b3.v[v], r4 = sy4 * b4.v[v];
+        const real r5 = sz5 * b5.v[v], r6 = sz6 * b6.v[v];
+        const real f1 = r1 + hx, f2 = r2 - hx;
+        const real f3 = r3 + hy, f4 = r4 - hy;
+        const real f5 = r5 + hz, f6 = r6 - hz;
         const real T = f0 + f1 + f2 + f3 + f4 + f5 + f6;
         const real jx = f1 - f2, jy = f3 - f4, jz = f5 - f6;
         const real *tb = tab + ph[v] * TABW;  // half of (I - tau^-1)
@@ -174,6 +179,14 @@ __device__ __forceinline__ void node_update(const Cell<real> &c, const real *__r
                 acc.v[R_QY] += qy;
                 acc.v[R_QZ] += qz;
                 acc.v[R_TSUM] += (double)T;
+                // rounding energy of this node: stored outputs minus the
+                // pulled inputs, both summed exactly in FP64 (the +-h
+                // shifts cancel within a node)
+                double din = (double)f0 + (double)r1 + (double)r2 + (double)r3 + (double)r4 + (double)r5 + (double)r6;
+                double dout = 0.0;
+#pragma unroll
+                for (int i = 0; i < Q; i++) dout += (double)out[i].v[v];
+                acc.v[R_LEAK] += dout - din;
                 if (!(dT <= 1e300)) acc.v[R_NONFINITE] += 1.0;
                 else acc.v[R_RESID] = fmax(acc.v[R_RESID], dT);
                 if constexpr (MODE == 3) {
@@ -210,7 +223,7 @@ __device__ __forceinline__ void node_update(const Cell<real> &c, const real *__r
         if (active) {
             real *__restrict__ d = c.dst;
 #pragma unroll
-            for (int i = 0; i < Q; i++) vstore<real, VEC>(d + i * N + base, out[i]);
+            for (int i = 0; i < Q; i++) vstore<real, VEC, (NT & 2) != 0>(d + i * N + base, out[i]);
         }
     }
 }

@@ -9,10 +9,10 @@
 namespace mrt {
 
 constexpr int Q = 7;
-constexpr int NRED = 8;  // reduced quantities per partial (see RedIdx)
+constexpr int NRED = 10;  // reduced quantities per partial (see RedIdx)
 constexpr int TABW = 12; // table reals per phase: half (I - tau^-1) [6], tau - I [6]
 
-enum RedIdx { R_PHI_HOT = 0, R_PHI_COLD, R_QX, R_QY, R_QZ, R_RESID, R_TSUM, R_NONFINITE };
+enum RedIdx { R_PHI_HOT = 0, R_PHI_COLD, R_QX, R_QY, R_QZ, R_RESID, R_TSUM, R_NONFINITE, R_LEAK, R_SPARE };
 
 // Per-medium geometry and boundary description passed to every kernel.
 // The state is stored as g_i = f_hat_i - w_i T_lin(x): the post-collision
@@ -34,6 +34,7 @@ struct Cell {
 
 struct Launch {
     int vec, bx, by;
+    int nt;  // bit 0: non-temporal state loads, bit 1: non-temporal state stores
 };
 
 // kernel launchers (lbm_kernels.hip)

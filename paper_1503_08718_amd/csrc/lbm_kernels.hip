@@ -50,7 +50,7 @@ __device__ __forceinline__ XLink chunk_links(const Cell<real> &c, int xv, int tx
     return xl;
 }
 
-template <typename real, int VEC>
+template <typename real, int VEC, int NT>
 __global__ void __launch_bounds__(256) k_step(Cell<real> c) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     real *tab = reinterpret_cast<real *>(smem_raw);
@@ -63,7 +63,7 @@ __global__ void __launch_bounds__(256) k_step(Cell<real> c) {
     xv = min(xv, c.nxv - 1);
     y = min(y, c.ny - 1);
     Acc dummy;
-    node_update<real, VEC, 0>(c, tab, xv, y, z, active, chunk_links<VEC>(c, xv, tx, bx), dummy, nullptr, real(0));
+    node_update<real, VEC, 0, NT>(c, tab, xv, y, z, active, chunk_links<VEC>(c, xv, tx, bx), dummy, nullptr, real(0));
 }
 
 // Observables (and optionally the step): the grid covers x and y like the
@@ -204,10 +204,20 @@ hipError_t launch_step(const Cell<real> &c, const Launch &L, hipStream_t s) {
     cc.nxv = c.nx / L.vec;
     const dim3 grid = step_grid(cc.nxv, c.ny, c.nz, L), block(L.bx, L.by);
     const size_t sh = sizeof(real) * TABW * c.nphase;
-    switch (L.vec) {
-        case 4: hipLaunchKernelGGL((k_step<real, 4>), grid, block, sh, s, cc); break;
-        case 2: hipLaunchKernelGGL((k_step<real, 2>), grid, block, sh, s, cc); break;
-        default: hipLaunchKernelGGL((k_step<real, 1>), grid, block, sh, s, cc); break;
+    switch (L.vec * 4 + (L.nt & 3)) {
+        case 16: hipLaunchKernelGGL((k_step<real, 4, 0>), grid, block, sh, s, cc); break;
+        case 17: hipLaunchKernelGGL((k_step<real, 4, 1>), grid, block, sh, s, cc); break;
+        case 18: hipLaunchKernelGGL((k_step<real, 4, 2>), grid, block, sh, s, cc); break;
+        case 19: hipLaunchKernelGGL((k_step<real, 4, 3>), grid, block, sh, s, cc); break;
+        case 8: hipLaunchKernelGGL((k_step<real, 2, 0>), grid, block, sh, s, cc); break;
+        case 9: hipLaunchKernelGGL((k_step<real, 2, 1>), grid, block, sh, s, cc); break;
+        case 10: hipLaunchKernelGGL((k_step<real, 2, 2>), grid, block, sh, s, cc); break;
+        case 11: hipLaunchKernelGGL((k_step<real, 2, 3>), grid, block, sh, s, cc); break;
+        case 4: hipLaunchKernelGGL((k_step<real, 1, 0>), grid, block, sh, s, cc); break;
+        case 5: hipLaunchKernelGGL((k_step<real, 1, 1>), grid, block, sh, s, cc); break;
+        case 6: hipLaunchKernelGGL((k_step<real, 1, 2>), grid, block, sh, s, cc); break;
+        case 7: hipLaunchKernelGGL((k_step<real, 1, 3>), grid, block, sh, s, cc); break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

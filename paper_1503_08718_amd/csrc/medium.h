@@ -56,7 +56,7 @@ struct mrtlbm_medium {
     int cur = 0;               // state in bufA (0) or bufB (1)
     long long steps = 0;
     bool initialised = false;
-    mrt::Launch launch{4, 64, 4};
+    mrt::Launch launch{4, 64, 4, 0};
     std::vector<mrt::GraphEntry> graphs;
 };
 

@@ -88,11 +88,11 @@ class Medium:
         check(load().mrtlbm_set_scale(self._h, float(dmax)))
         return self
 
-    def set_launch(self, vec=None, bx=None, by=None):
+    def set_launch(self, vec=None, bx=None, by=None, nt=0):
         if vec is None:
             check(load().mrtlbm_set_launch(self._h, None))
         else:
-            check(load().mrtlbm_set_launch(self._h, ctypes.byref(Launch(vec, bx, by))))
+            check(load().mrtlbm_set_launch(self._h, ctypes.byref(Launch(vec, bx, by, nt))))
         return self
 
     def info(self) -> dict:
@@ -100,12 +100,12 @@ class Medium:
         n = ctypes.c_longlong()
         L = Launch()
         check(load().mrtlbm_info(self._h, ctypes.byref(s), ctypes.byref(n), ctypes.byref(L)))
-        return dict(scale=s.value, steps=n.value, launch=(L.vec, L.bx, L.by))
+        return dict(scale=s.value, steps=n.value, launch=(L.vec, L.bx, L.by, L.nt))
 
     def autotune(self, cache_path: str | None = None):
         L = Launch()
         check(load().mrtlbm_autotune(self._h, cache_path.encode() if cache_path else None, ctypes.byref(L)))
-        return (L.vec, L.bx, L.by)
+        return (L.vec, L.bx, L.by, L.nt)
 
     def load_tuned(self, cache_path: str) -> bool:
         st = check(load().mrtlbm_load_tuned(self._h, cache_path.encode()), allow=(0, 1))
