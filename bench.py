@@ -1,13 +1,23 @@
 #!/usr/bin/env python3
-"""Benchmark: lattice updates per second of the fused collide-and-stream
-step on a synthetic four-directional braided unit cell, on one GPU.
+"""Benchmarks of the MI355X lattice Boltzmann conductivity solver (one GPU).
 
-One benchmark "step" is one lattice Boltzmann step over the whole cell,
-including the FP64 check-step reductions at the production interval
-(one observable evaluation every ``--check-every`` steps).  The line printed
-by rank 0 carries the HBM roofline of the step kernel (achieved algorithmic
-GB/s against MI355X's 8 TB/s) and the CPU oracle's throughput on a bounded
-sample of the same workload.
+Default mode (the contract line): lattice updates per second of the fused
+collide-and-stream step on a synthetic four-directional braided unit cell
+(256^3, FP32).  One benchmark "step" is one lattice Boltzmann step over the
+whole cell, including the FP64 check-step reductions at the production
+interval (one observable evaluation every ``--check-every`` steps).  The line
+carries the HBM roofline of the step kernel (algorithmic bytes per update /
+kernel time, against MI355X's 8 TB/s) and the CPU oracle's throughput on a
+bounded sample of the same workload.
+
+Other modes (each prints one JSON line):
+  --mode copy       a plain 1 GiB device copy, the calibration of HBM counters
+  --mode solve      steady-state solves of one braided cell (k_T: x gradient,
+                    k_L: z gradient), FP32 against an FP64 reference
+  --mode sweep      the parametric sweep of braided cells of uneven size,
+                    batched, to k_eff at 1e-4: unit cells per hour
+  --mode warmstart  held-out cells solved from a zero start and from the
+                    learned warm start: steps and cells per hour
 """
 
 from __future__ import annotations
@@ -23,12 +33,18 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TUNE_CACHE = os.path.join(ROOT, "paper_1503_08718_amd", "tuned_launch.txt")
 WORKLOADS = {
-    # name: (n, precision, bytes per lattice update of the step kernel)
+    # name: (n, precision, algorithmic bytes per lattice update of the step kernel)
     "braid256_f32": (256, "f32", 57.0),
     "braid128_f32": (128, "f32", 57.0),
     "braid256_f64": (256, "f64", 113.0),
+    "braid128_f64": (128, "f64", 113.0),
 }
+# HBM bytes per k_step launch on braid256_f32 from rocprofv3 --pmc FETCH_SIZE /
+# WRITE_SIZE (KiB per dispatch), each scaled by the counter's reading for a
+# plain copy of known size; None once the kernel changes.
+MEASURED_TRAFFIC = {}
 
 
 def parse():
@@ -36,16 +52,41 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=4000)
     p.add_argument("--warmup", type=int, default=400)
+    p.add_argument("--mode", default="throughput", choices=["throughput", "copy", "solve", "sweep", "warmstart"])
     p.add_argument("--workload", default="braid256_f32", choices=sorted(WORKLOADS))
     p.add_argument("--check-every", type=int, default=200)
-    p.add_argument("--launch", default="", help="vec,bx,by (default: autotune cache or built-in)")
-    p.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1503_08718_amd", "tuned_launch.txt"))
+    p.add_argument("--launch", default="", help="vec,bx,by[,nt] (default: autotune cache, else built-in)")
+    p.add_argument("--tune-cache", default=TUNE_CACHE)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-steps", type=int, default=0, help="oracle steps on the full cell (0 = auto)")
+    # solve / sweep / warmstart
+    p.add_argument("--n", type=int, default=128)
+    p.add_argument("--gamma", type=float, default=30.0)
+    p.add_argument("--vf", type=float, default=0.5)
+    p.add_argument("--axes", default="0,2")
+    p.add_argument("--sides", default="periodic", choices=["periodic", "adiabatic"])
+    p.add_argument("--tol", type=float, default=1e-4)
+    p.add_argument("--ref-tol", type=float, default=1e-7)
+    p.add_argument("--no-ref", action="store_true")
+    p.add_argument("--max-steps", type=int, default=20_000_000)
+    p.add_argument("--cells", type=int, default=64)
+    p.add_argument("--seed", type=int, default=1503)
+    p.add_argument("--model", default=os.path.join(ROOT, "paper_1503_08718_amd", "warmstart_model.pt"))
     return p.parse_args()
 
 
-def cpu_baseline(m, prec_bytes, sample_steps):
+def _medium(m, prec, args):
+    from paper_1503_08718_amd.solver import Medium
+
+    g = Medium(m.phase, m.k, precision=prec, device="cuda:0")
+    if args.launch:
+        g.set_launch(*[int(v) for v in args.launch.split(",")])
+    elif os.path.exists(args.tune_cache):
+        g.load_tuned(args.tune_cache)
+    return g
+
+
+def cpu_baseline(m, sample_steps):
     """The oracle, as it is, on a bounded sample of the same cell."""
     import oracle
 
@@ -59,51 +100,40 @@ def cpu_baseline(m, prec_bytes, sample_steps):
     o.step(steps)
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-    return {"value": n * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+    return {"value": round(n * steps / dt / 1e6, 2), "unit": "MLUPS", "cores": cores, "kind": "oracle",
             "sample": f"{steps} FP64 oracle steps on the same {m.nx}x{m.ny}x{m.nz} braided cell "
                       f"(x gradient, periodic sides), OpenMP over z-planes"}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1 (a single cell is not sharded)"}))
-        sys.exit(2)
+def mode_throughput(args):
     import torch
 
     import workloads
-    from paper_1503_08718_amd import load
-    from paper_1503_08718_amd.solver import Medium
 
-    load()
     n, prec, bpl = WORKLOADS[args.workload]
     m = workloads.braid(n, n, n, 30.0, 0.5)
-    g = Medium(m.phase, m.k, precision=prec, device="cuda:0")
+    g = _medium(m, prec, args)
     g.set_bc(0, 1.0, 0.0, ("periodic", "periodic", "periodic"))
-    if args.launch:
-        g.set_launch(*[int(v) for v in args.launch.split(",")])  # vec,bx,by[,nt]
-    elif os.path.exists(args.tune_cache):
-        g.load_tuned(args.tune_cache)
     g.init()
     K = args.check_every
     # warm-up: the same graphs the timed region replays
     g.solve(1e-30, "keff", args.warmup, check_every=K)
     torch.cuda.synchronize()
-    # timed region: whole job = steps with a check every K steps; the kernel
-    # time of the plain step is taken from hip events around plain steps
     t0 = time.perf_counter()
     r = g.solve(1e-30, "keff", args.warmup + args.steps, check_every=K)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     nodes = n ** 3
     mlups = nodes * args.steps / wall / 1e6
-    # live kernel timing with hip events on the medium's stream (plain steps only)
+    # live kernel time: hip events around plain steps on the medium's stream
     kt_steps = max(64, min(args.steps, 2000))
     ms = g.time_steps(kt_steps)
     kern_us = ms * 1e3 / kt_steps
     achieved = bpl * nodes / (kern_us * 1e-6) / 1e9
+    launch = dict(zip(("vec", "bx", "by", "nt"), g.info()["launch"]))
+    traffic = MEASURED_TRAFFIC.get((args.workload, tuple(launch.values())))
     line = {
-        "metric": "MLUPS (lattice updates per second, millions) of the fused collide+stream step, with % of HBM peak",
+        "metric": "MLUPS (million lattice updates per second) of the fused collide+stream step, with % of HBM peak",
         "value": round(mlups, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -120,7 +150,7 @@ def main():
                         f"k_axial 10 / k_trans 1 / matrix 0.2, x gradient, periodic sides, {prec.upper()}",
             "nodes": nodes,
             "check_every": K,
-            "launch": dict(zip(("vec", "bx", "by", "nt"), g.info()["launch"])),
+            "launch": launch,
         },
         "roofline": {
             "bound": "hbm",
@@ -128,15 +158,136 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic,
             "kernel": "k_step",
             "kernel_us": round(kern_us, 3),
             "bytes_per_update": bpl,
+            "algorithmic_bytes_per_launch": int(bpl * nodes),
         },
         "keff_after": round(r["keff"], 6),
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(m, bpl, args.cpu_sample_steps)
+        line["cpu_baseline"] = cpu_baseline(m, args.cpu_sample_steps)
+    return line
+
+
+def mode_copy(args):
+    import torch
+
+    n = 1 << 28  # 1 GiB of float32
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    reps = 20
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    return {"mode": "copy", "bytes_read_per_copy": 4 * n, "bytes_written_per_copy": 4 * n, "copies": reps + 3,
+            "GB_s": round(8 * n / dt / 1e9, 1)}
+
+
+def _solve(m, prec, axis, sides, tol, args, T0=None, flux=False):
+    import torch
+
+    g = _medium(m, prec, args)
+    g.set_bc(axis, 1.0, 0.0, (sides,) * 3)
+    g.init(T0, flux=flux)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = g.solve(tol, "keff", args.max_steps, check_every=1000)
+    torch.cuda.synchronize()
+    r["seconds"] = round(time.perf_counter() - t0, 3)
+    return g, r
+
+
+def mode_solve(args):
+    import workloads
+
+    m = workloads.braid(args.n, args.n, args.n, args.gamma, args.vf)
+    out = {"mode": "solve", "workload": f"braided cell {args.n}^3, gamma {args.gamma}, yarn fraction {args.vf}, "
+                                        f"{args.sides} sides", "tol": args.tol, "solves": []}
+    keys32 = ("keff", "keff_hot", "keff_cold", "keff_vol", "keff_col", "keff_leak", "steps", "seconds", "status")
+    for axis in [int(a) for a in args.axes.split(",")]:
+        g32, r32 = _solve(m, "f32", axis, args.sides, args.tol, args)
+        rec = {"axis": "xyz"[axis], "f32": {k: r32[k] for k in keys32}}
+        if not args.no_ref:
+            # FP64 reference, started from the FP32 field (with its flux part)
+            T = g32.temperature().double()
+            g64, r64 = _solve(m, "f64", axis, args.sides, args.ref_tol, args, T0=T, flux=True)
+            rec["f64_ref"] = {k: r64[k] for k in ("keff", "keff_hot", "keff_cold", "keff_vol", "steps", "seconds",
+                                                  "status")}
+            rec["f32_rel_err"] = abs(r32["keff"] - r64["keff"]) / abs(r64["keff"])
+            rec["f32_rel_err_vol"] = abs(r32["keff_vol"] - r64["keff_vol"]) / abs(r64["keff_vol"])
+        out["solves"].append(rec)
+        print(json.dumps(rec), flush=True)
+    return out
+
+
+def mode_sweep(args):
+    import torch
+
+    import workloads
+    from paper_1503_08718_amd.solver import batch_solve
+
+    t_start = time.perf_counter()
+    specs = workloads.sweep_cells(args.seed, args.cells)
+    media = [workloads.braid(c["nx"], c["ny"], c["nz"], c["gamma"], c["v"]) for c in specs]
+    t_gen = time.perf_counter() - t_start
+    results = {}
+    steps = {}
+    for axis in [int(a) for a in args.axes.split(",")]:
+        cells = []
+        for m in media:
+            g = _medium(m, "f32", args)
+            g.set_bc(axis, 1.0, 0.0, ("periodic",) * 3)
+            g.init()
+            cells.append(g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res, st = batch_solve(cells, tol=args.tol, kind="keff", max_steps=args.max_steps, check_every=1000)
+        torch.cuda.synchronize()
+        results[axis] = (res, st, time.perf_counter() - t0)
+        steps[axis] = [r["steps"] for r in res]
+        print(json.dumps({"axis": "xyz"[axis], "status": st, "seconds": round(results[axis][2], 2)}), flush=True)
+        del cells
+    wall = time.perf_counter() - t_start
+    conv = all(r["converged"] for res, _, _ in results.values() for r in res)
+    nodes = sum(m.phase.size for m in media)
+    lu = sum(m.phase.size * s for axis in steps for m, s in zip(media, steps[axis]))
+    return {"mode": "sweep", "cells": len(media), "nodes_total": nodes, "all_converged": conv,
+            "tol": args.tol, "axes": args.axes, "seconds_total": round(wall, 2),
+            "seconds_geometry": round(t_gen, 2),
+            "seconds_per_axis": {"xyz"[a]: round(v[2], 2) for a, v in results.items()},
+            "cells_per_hour": round(len(media) / (wall / 3600.0), 1),
+            "effective_MLUPS": round(lu / sum(v[2] for v in results.values()) / 1e6, 1),
+            "steps_per_cell": {"xyz"[a]: [min(s), max(s)] for a, s in steps.items()},
+            "keff": {"xyz"[a]: [round(r["keff"], 6) for r in v[0]] for a, v in results.items()}}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1 (a single cell is not sharded)"}))
+        sys.exit(2)
+    from paper_1503_08718_amd import load
+
+    load()
+    if args.mode == "throughput":
+        line = mode_throughput(args)
+    elif args.mode == "copy":
+        line = mode_copy(args)
+    elif args.mode == "solve":
+        line = mode_solve(args)
+    elif args.mode == "sweep":
+        line = mode_sweep(args)
+    else:
+        from paper_1503_08718_amd import warmstart
+
+        line = warmstart.bench(args)
     print(json.dumps(line), flush=True)
 
 

@@ -44,7 +44,7 @@ bool batch_layout(mrtlbm_medium *const *cells, int n, BatchLayout *L) {
 struct BatchRun {
     mrtlbm_medium *const *cells;
     int n;
-    int vec, threads, max_nphase;
+    int vec, threads, max_nphase, nt;
     char *ws;
     BatchLayout lay;
     hipStream_t stream, cap;
@@ -110,8 +110,8 @@ mrtlbm_status build_graph(BatchRun &B, int K) {
     hipError_t e = hipStreamBeginCapture(B.cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     for (int i = 0; i < K && e == hipSuccess; i++)
-        e = launch_batch<real>(cells, tiles, B.ntiles, B.vec, B.threads, B.max_nphase, i & 1, i == K - 1, partials,
-                               B.cap);
+        e = launch_batch<real>(cells, tiles, B.ntiles, B.vec, B.threads, B.max_nphase, i & 1, i == K - 1, B.nt,
+                               partials, B.cap);
     if (e == hipSuccess) e = launch_batch_reduce(partials, start, (int)B.active.size(), finals, B.cap);
     if (e == hipSuccess)
         e = hipMemcpyAsync(B.pinned, finals, B.active.size() * NRED * sizeof(double), hipMemcpyDeviceToHost, B.cap);
@@ -216,6 +216,7 @@ extern "C" mrtlbm_status mrtlbm_batch_solve(mrtlbm_medium *const *cells, int n, 
     B.vec = vec;
     B.threads = threads;
     B.max_nphase = max_nphase;
+    B.nt = m0->launch.nt;
     B.ws = (char *)workspace_dev;
     B.lay = lay;
     B.stream = m0->stream;
