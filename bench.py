@@ -44,7 +44,7 @@ WORKLOADS = {
 # HBM bytes per k_step launch on braid256_f32 from rocprofv3 --pmc FETCH_SIZE /
 # WRITE_SIZE (KiB per dispatch), each scaled by the counter's reading for a
 # plain copy of known size; None once the kernel changes.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {("braid256_f32", (4, 64, 2, 3)): 956408366}
 
 
 def parse():

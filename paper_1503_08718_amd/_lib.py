@@ -72,6 +72,11 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+    # torch carries its own HIP runtime under the same soname; loading torch
+    # first makes the library bind to that runtime, so the process holds one
+    # HIP runtime (two would each try to own the device)
+    import torch  # noqa: F401
+
     L = ctypes.CDLL(LIB_PATH)
     P, I, D, LL, SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong, ctypes.c_size_t
     PP = ctypes.POINTER(ctypes.c_void_p)
