@@ -274,8 +274,11 @@ def main():
         print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1 (a single cell is not sharded)"}))
         sys.exit(2)
     from paper_1503_08718_amd import load
+    from paper_1503_08718_amd._lib import set_progress
 
     load()
+    if args.mode != "throughput":
+        set_progress(lambda msg: print(msg, file=sys.stderr, flush=True), 30.0)
     if args.mode == "throughput":
         line = mode_throughput(args)
     elif args.mode == "copy":

@@ -191,6 +191,13 @@ mrtlbm_status mrtlbm_time_steps(mrtlbm_medium *m, long long nsteps, double *ms);
 void mrtlbm_destroy(mrtlbm_medium *m);
 const char *mrtlbm_last_error(void);
 
+/* Progress reports of long solves: when set, mrtlbm_solve and
+ * mrtlbm_batch_solve call fn(message, user) from the calling thread at check
+ * points, at most once every interval_s seconds.  NULL switches it off.
+ * Process-wide. */
+typedef void (*mrtlbm_progress_fn)(const char *message, void *user);
+void mrtlbm_set_progress(mrtlbm_progress_fn fn, void *user, double interval_s);
+
 /* ------------------------------------------------------------------------ */
 /* Batched many-cell solver                                                  */
 /* ------------------------------------------------------------------------ */

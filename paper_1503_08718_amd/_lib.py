@@ -51,6 +51,21 @@ class Launch(ctypes.Structure):
 
 
 _lib = None
+PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_char_p, ctypes.c_void_p)
+_progress_keep = None
+
+
+def set_progress(fn=None, interval_s: float = 30.0):
+    """Report long solves: fn(message: str) is called at check points, at
+    most every interval_s seconds (None switches reports off)."""
+    global _progress_keep
+    L = load()
+    if fn is None:
+        _progress_keep = None
+        L.mrtlbm_set_progress(PROGRESS_FN(), None, 0.0)
+        return
+    _progress_keep = PROGRESS_FN(lambda msg, user: fn(msg.decode()))
+    L.mrtlbm_set_progress(_progress_keep, None, float(interval_s))
 
 
 def declared_symbols() -> list[str]:
@@ -105,6 +120,27 @@ def load():
         "mrtlbm_batch_workspace_bytes": (SZ, [PP, I]),
         "mrtlbm_batch_solve": (I, [PP, I, D, I, LL, I, P, SZ, RP]),
     }
+    F = ctypes.c_float
+    FP = ctypes.POINTER(ctypes.c_float)
+    sig.update({
+        "mrtlbm_nn_kpad": (I, [I]),
+        "mrtlbm_nn_conv3d_fwd": (I, [P, I, I, I, I, I, P, P, I, I, I, P, P, P]),
+        "mrtlbm_nn_conv3d_dgrad": (I, [P, I, I, I, I, I, P, I, I, P, P, P]),
+        "mrtlbm_nn_wgrad_scratch_bytes": (SZ, [I, I, I, I, I, I]),
+        "mrtlbm_nn_conv3d_wgrad": (I, [P, P, I, I, I, I, I, I, I, P, P, P, P]),
+        "mrtlbm_nn_relu_bwd": (I, [P, P, P, LL, P]),
+        "mrtlbm_nn_add": (I, [P, P, P, LL, P]),
+        "mrtlbm_nn_pool2": (I, [I, P, I, I, I, I, I, P, P]),
+        "mrtlbm_nn_up2": (I, [I, P, I, I, I, I, I, P, P]),
+        "mrtlbm_nn_mse": (I, [P, I, P, LL, P, P, P, P]),
+        "mrtlbm_nn_adam": (I, [P, P, P, P, LL, F, F, F, F, I, P, P]),
+        "mrtlbm_nn_to_bf16": (I, [P, LL, P, P]),
+        "mrtlbm_nn_features": (I, [P, I, I, I, P, P, P]),
+        "mrtlbm_nn_target": (I, [P, I, I, I, F, P, P]),
+        "mrtlbm_nn_to_temperature": (I, [P, I, I, I, I, I, F, F, P, P, ctypes.POINTER(ctypes.c_longlong), P]),
+    })
+    del FP
+    sig["mrtlbm_set_progress"] = (None, [PROGRESS_FN, P, D])
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
         fn.restype = res

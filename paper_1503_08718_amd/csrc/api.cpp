@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -40,6 +41,31 @@ mrtlbm_status mrt::hip_fail(hipError_t e, const char *what) {
 }
 
 extern "C" const char *mrtlbm_last_error(void) { return g_err.c_str(); }
+
+static mrtlbm_progress_fn g_progress = nullptr;
+static void *g_progress_user = nullptr;
+static double g_progress_interval = 30.0;
+static std::chrono::steady_clock::time_point g_progress_last;
+
+extern "C" void mrtlbm_set_progress(mrtlbm_progress_fn fn, void *user, double interval_s) {
+    g_progress = fn;
+    g_progress_user = user;
+    g_progress_interval = interval_s > 0 ? interval_s : 0.0;
+    g_progress_last = std::chrono::steady_clock::now();
+}
+
+void mrt::progress(const char *fmt, ...) {
+    if (!g_progress) return;
+    const auto now = std::chrono::steady_clock::now();
+    if (std::chrono::duration<double>(now - g_progress_last).count() < g_progress_interval) return;
+    g_progress_last = now;
+    char buf[256];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_progress(buf, g_progress_user);
+}
 
 #define HIPCHK(call)                                      \
     do {                                                  \
@@ -576,6 +602,8 @@ static mrtlbm_status do_solve(mrtlbm_medium *m, double tol, mrtlbm_tol_kind kind
         HIPCHK(hipStreamSynchronize(m->stream));
         fill_result(m, m->pinned, &r);
         const int v = stop_rule(ss, r, tol, kind);
+        progress("solve: step %lld, k_hot %.8g, k_cold %.8g, k_leak %.3g, resid %.3g", r.steps, r.keff_hot,
+                 r.keff_cold, r.keff_leak, r.resid);
         if (v == -1) { *out = r; return fail(MRTLBM_E_NONFINITE, "%d non-finite nodes at step %lld", r.nonfinite, r.steps); }
         if (v == -2) { *out = r; return fail(MRTLBM_E_DIVERGED, "residual %g grew from %g", r.resid, ss.min_resid); }
         if (v == 1) {

@@ -162,6 +162,7 @@ mrtlbm_status run(BatchRun &B, double tol, mrtlbm_tol_kind kind, long long max_s
             else if (m->steps + K > max_steps) state[i] = 2;
             else still.push_back(i);
         }
+        progress("batch: %zu of %d cells still active after this check (%d tiles)", still.size(), B.n, B.ntiles);
         if (still.size() != B.active.size()) rebuild = true;
         B.active.swap(still);
     }

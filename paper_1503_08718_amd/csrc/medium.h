@@ -25,6 +25,8 @@ struct StopState {
 };
 
 mrtlbm_status fail(mrtlbm_status st, const char *fmt, ...);
+// rate-limited progress report through the callback set by mrtlbm_set_progress
+void progress(const char *fmt, ...);
 mrtlbm_status hip_fail(hipError_t e, const char *what);
 size_t partial_capacity(int nx, int ny);
 

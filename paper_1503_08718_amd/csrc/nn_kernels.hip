@@ -1,0 +1,525 @@
+// Kernels of the learned warm start: a small 3-D convolutional
+// encoder-decoder trained on steady temperature fields the solver produces.
+//
+// Activations are BF16, channels-last [n][z][y][x][c]; weights of a 3x3x3
+// convolution are BF16 [cout][Kpad] with k = tap * cin + ci, tap = (dz*3 +
+// dy)*3 + dx for offsets -1..1, zero-padded to Kpad = 32 * ceil(27 cin / 32);
+// accumulation is FP32 on the matrix cores (v_mfma_f32_16x16x32_bf16).
+// Convolution = implicit GEMM: M = voxels, N = cout, K = 27 cin.  A lane of a
+// 16x16x32 product holds 8 consecutive k of one row, i.e. 8 channels of one
+// tap: one 16-byte load of the channels-last activations.
+// Padding per axis: circular (periodic cell sides) or zero (the walls of the
+// gradient axis).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "nn_internal.h"
+
+namespace mrt {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+
+
+// neighbour voxel of v (flattened over n, z, y, x) at tap offset; -1 if it
+// falls into zero padding
+__device__ __forceinline__ long long neighbour(const ConvGeom &g, long long v, int tap) {
+    const int x = (int)(v % g.W);
+    long long r = v / g.W;
+    const int y = (int)(r % g.H);
+    r /= g.H;
+    const int z = (int)(r % g.D);
+    const long long nb = r / g.D;
+    int px = x + tap % 3 - 1, py = y + (tap / 3) % 3 - 1, pz = z + tap / 9 - 1;
+    if (px < 0 || px >= g.W) { if (!(g.circ & 1)) return -1; px = (px + g.W) % g.W; }
+    if (py < 0 || py >= g.H) { if (!(g.circ & 2)) return -1; py = (py + g.H) % g.H; }
+    if (pz < 0 || pz >= g.D) { if (!(g.circ & 4)) return -1; pz = (pz + g.D) % g.D; }
+    return ((nb * g.D + pz) * g.H + py) * g.W + px;
+}
+
+__device__ __forceinline__ bf16x8 zero8() {
+    bf16x8 z;
+#pragma unroll
+    for (int e = 0; e < 8; e++) z[e] = (bf16)0.0f;
+    return z;
+}
+
+// one wave: 16*MT voxels x 16*NT output channels; 4 waves per block along voxels
+template <int MT, int NT>
+__global__ void __launch_bounds__(256) k_conv_fwd(const bf16 *__restrict__ in, const bf16 *__restrict__ w,
+                                                  const float *__restrict__ bias, ConvGeom g, int relu,
+                                                  bf16 *__restrict__ out, float *__restrict__ out_f32) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long long nvox = (long long)g.n * g.D * g.H * g.W;
+    const long long v0 = ((long long)blockIdx.x * 4 + wave) * (16 * MT);
+    const int n0 = blockIdx.y * (16 * NT);
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int i = 0; i < MT; i++)
+#pragma unroll
+        for (int j = 0; j < NT; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    long long vrow[MT];
+#pragma unroll
+    for (int i = 0; i < MT; i++) {
+        const long long v = v0 + i * 16 + (lane & 15);
+        vrow[i] = v < nvox ? v : nvox - 1;
+    }
+    const int kq = (lane >> 4) * 8;  // this lane's first k inside a 32-wide chunk
+    const int K27 = 27 * g.cin;
+    for (int k0 = 0; k0 < g.kpad; k0 += 32) {
+        const int k = k0 + kq;
+        bf16x8 a[MT], b[NT];
+        const int tap = k / g.cin, c0 = k - tap * g.cin;
+#pragma unroll
+        for (int i = 0; i < MT; i++) {
+            long long p = (k < K27) ? neighbour(g, vrow[i], tap) : -1;
+            a[i] = (p >= 0) ? *reinterpret_cast<const bf16x8 *>(in + p * g.cin + c0) : zero8();
+        }
+#pragma unroll
+        for (int j = 0; j < NT; j++) {
+            const int co = n0 + j * 16 + (lane & 15);
+            b[j] = *reinterpret_cast<const bf16x8 *>(w + (long long)co * g.kpad + k);
+        }
+#pragma unroll
+        for (int i = 0; i < MT; i++)
+#pragma unroll
+            for (int j = 0; j < NT; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    // result of a 16x16 tile: lane holds rows 4*(lane/16) + r, column lane % 16
+#pragma unroll
+    for (int i = 0; i < MT; i++)
+#pragma unroll
+        for (int j = 0; j < NT; j++) {
+            const int co = n0 + j * 16 + (lane & 15);
+            const float bb = bias ? bias[co] : 0.0f;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const long long v = v0 + i * 16 + (lane >> 4) * 4 + r;
+                if (v >= nvox) continue;
+                float y = acc[i][j][r] + bb;
+                if (relu) y = fmaxf(y, 0.0f);
+                if (out_f32) out_f32[v * g.cout + co] = y;
+                else out[v * g.cout + co] = (bf16)y;
+            }
+        }
+}
+
+// weights of the adjoint convolution: wt[ci][flip(tap) * cout + co] = w[co][tap * cin + ci]
+__global__ void k_weight_flip(const bf16 *__restrict__ w, int cin, int cout, int kpad, int kpad_t, bf16 *__restrict__ wt) {
+    const long long total = (long long)cin * kpad_t;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
+        const int ci = (int)(i / kpad_t), kt = (int)(i % kpad_t);
+        bf16 val = (bf16)0.0f;
+        if (kt < 27 * cout) {
+            const int tapt = kt / cout, co = kt % cout;
+            val = w[(long long)co * kpad + (26 - tapt) * cin + ci];
+        }
+        wt[i] = val;
+    }
+}
+
+// weight gradient, split over voxels: partials[s][co][k] = sum over this
+// split's voxels of dy[v][co] * x[neighbour(v, tap)][ci].  One wave per block:
+// 16 output channels x 32 k (two 16-wide column tiles).
+__global__ void __launch_bounds__(64) k_conv_wgrad(const bf16 *__restrict__ x, const bf16 *__restrict__ dy, ConvGeom g,
+                                                   long long vox_per_split, float *__restrict__ partials) {
+    const int lane = threadIdx.x;
+    const int ktile = blockIdx.x, cotile = blockIdx.y, s = blockIdx.z;
+    const long long nvox = (long long)g.n * g.D * g.H * g.W;
+    const long long vb = s * vox_per_split;
+    const long long ve = min(nvox, vb + vox_per_split);
+    const int co = cotile * 16 + (lane & 15);
+    const int K27 = 27 * g.cin;
+    int kcol[2], tap[2], ci[2];
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+        kcol[j] = ktile * 32 + j * 16 + (lane & 15);
+        tap[j] = kcol[j] / g.cin;
+        ci[j] = kcol[j] - tap[j] * g.cin;
+    }
+    f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+    for (long long v0 = vb; v0 < ve; v0 += 32) {
+        const long long vq = v0 + (lane >> 4) * 8;
+        bf16x8 a, b[2];
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            const long long v = vq + e;
+            a[e] = (v < ve) ? dy[v * g.cout + co] : (bf16)0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                const long long v = vq + e;
+                bf16 val = (bf16)0.0f;
+                if (v < ve && kcol[j] < K27) {
+                    const long long p = neighbour(g, v, tap[j]);
+                    if (p >= 0) val = x[p * g.cin + ci[j]];
+                }
+                b[j][e] = val;
+            }
+#pragma unroll
+        for (int j = 0; j < 2; j++) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[j], 0, 0, 0);
+    }
+    // tile rows = output channels, columns = k
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int orow = cotile * 16 + (lane >> 4) * 4 + r;
+            const int kc = ktile * 32 + j * 16 + (lane & 15);
+            partials[((long long)s * g.cout + orow) * g.kpad + kc] = acc[j][r];
+        }
+}
+
+// fixed-order sum over splits; optional accumulate into dw
+__global__ void k_sum_splits(const float *__restrict__ partials, long long len, int splits, float *__restrict__ out) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < len; i += (long long)gridDim.x * blockDim.x) {
+        float acc = 0.0f;
+        for (int s = 0; s < splits; s++) acc += partials[(long long)s * len + i];
+        out[i] = acc;
+    }
+}
+
+__global__ void k_sum_rows(const float *__restrict__ p, int rows, float scale, float *__restrict__ out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        float acc = 0.0f;
+        for (int i = 0; i < rows; i++) acc += p[i];
+        out[0] = acc * scale;
+    }
+}
+
+// bias gradient partials: partials[s][c] = sum over the split's voxels of dy[v][c]
+__global__ void k_bias_grad(const bf16 *__restrict__ dy, long long nvox, int c, long long vox_per_split,
+                            float *__restrict__ partials) {
+    const int s = blockIdx.x;
+    const long long vb = s * vox_per_split, ve = min(nvox, vb + vox_per_split);
+    for (int ch = threadIdx.x; ch < c; ch += blockDim.x) {
+        float acc = 0.0f;
+        for (long long v = vb; v < ve; v++) acc += (float)dy[v * c + ch];
+        partials[(long long)s * c + ch] = acc;
+    }
+}
+
+__global__ void k_relu_bwd(const bf16 *__restrict__ y, const bf16 *__restrict__ dy, bf16 *__restrict__ dx, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dx[i] = ((float)y[i] > 0.0f) ? dy[i] : (bf16)0.0f;
+}
+
+__global__ void k_add(const bf16 *__restrict__ a, const bf16 *__restrict__ b, bf16 *__restrict__ out, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        out[i] = (bf16)((float)a[i] + (float)b[i]);
+}
+
+// 2x2x2 average pooling, channels-last; (D, H, W) are the input extents
+__global__ void k_pool2_fwd(const bf16 *__restrict__ in, int n, int D, int H, int W, int c, bf16 *__restrict__ out) {
+    const int Do = D / 2, Ho = H / 2, Wo = W / 2;
+    const long long total = (long long)n * Do * Ho * Wo * c;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
+        const int ch = (int)(i % c);
+        long long r = i / c;
+        const int x = (int)(r % Wo); r /= Wo;
+        const int y = (int)(r % Ho); r /= Ho;
+        const int z = (int)(r % Do);
+        const long long nb = r / Do;
+        float acc = 0.0f;
+        for (int dz = 0; dz < 2; dz++)
+            for (int dy = 0; dy < 2; dy++)
+                for (int dx = 0; dx < 2; dx++)
+                    acc += (float)in[((((nb * D + 2 * z + dz) * H) + 2 * y + dy) * W + 2 * x + dx) * c + ch];
+        out[i] = (bf16)(acc * 0.125f);
+    }
+}
+
+__global__ void k_pool2_bwd(const bf16 *__restrict__ dout, int n, int D, int H, int W, int c, bf16 *__restrict__ din) {
+    const long long total = (long long)n * D * H * W * c;
+    const int Do = D / 2, Ho = H / 2, Wo = W / 2;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
+        const int ch = (int)(i % c);
+        long long r = i / c;
+        const int x = (int)(r % W); r /= W;
+        const int y = (int)(r % H); r /= H;
+        const int z = (int)(r % D);
+        const long long nb = r / D;
+        din[i] = (bf16)((float)dout[(((nb * Do + z / 2) * Ho + y / 2) * Wo + x / 2) * c + ch] * 0.125f);
+    }
+}
+
+// nearest 2x upsampling; (D, H, W) are the input extents
+__global__ void k_up2_fwd(const bf16 *__restrict__ in, int n, int D, int H, int W, int c, bf16 *__restrict__ out) {
+    const int D2 = 2 * D, H2 = 2 * H, W2 = 2 * W;
+    const long long total = (long long)n * D2 * H2 * W2 * c;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
+        const int ch = (int)(i % c);
+        long long r = i / c;
+        const int x = (int)(r % W2); r /= W2;
+        const int y = (int)(r % H2); r /= H2;
+        const int z = (int)(r % D2);
+        const long long nb = r / D2;
+        out[i] = in[(((nb * D + z / 2) * H + y / 2) * W + x / 2) * c + ch];
+    }
+}
+
+__global__ void k_up2_bwd(const bf16 *__restrict__ dout, int n, int D, int H, int W, int c, bf16 *__restrict__ din) {
+    const long long total = (long long)n * D * H * W * c;
+    const int H2 = 2 * H, W2 = 2 * W, D2 = 2 * D;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
+        const int ch = (int)(i % c);
+        long long r = i / c;
+        const int x = (int)(r % W); r /= W;
+        const int y = (int)(r % H); r /= H;
+        const int z = (int)(r % D);
+        const long long nb = r / D;
+        float acc = 0.0f;
+        for (int dz = 0; dz < 2; dz++)
+            for (int dy = 0; dy < 2; dy++)
+                for (int dx = 0; dx < 2; dx++)
+                    acc += (float)dout[((((nb * D2 + 2 * z + dz) * H2) + 2 * y + dy) * W2 + 2 * x + dx) * c + ch];
+        din[i] = (bf16)acc;
+    }
+}
+
+// mean squared error of channel 0 of pred[v][cpred] against target[v];
+// dpred[v][c] = 2 (pred - target) / nvox on channel 0, zero elsewhere;
+// partials[block] = sum of squares of the block's voxels
+__global__ void __launch_bounds__(256) k_mse(const float *__restrict__ pred, int cpred, const float *__restrict__ target,
+                                             long long nvox, bf16 *__restrict__ dpred, float *__restrict__ partials) {
+    __shared__ float red[256];
+    float acc = 0.0f;
+    for (long long v = blockIdx.x * 256LL + threadIdx.x; v < nvox; v += (long long)gridDim.x * 256) {
+        const float d = pred[v * cpred] - target[v];
+        acc += d * d;
+        dpred[v * cpred] = (bf16)(2.0f * d / (float)nvox);
+        for (int ch = 1; ch < cpred; ch++) dpred[v * cpred + ch] = (bf16)0.0f;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+// Adam on FP32 master weights; also writes the BF16 copy used by the kernels
+__global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m, float *__restrict__ v,
+                       long long n, float lr, float b1, float b2, float eps, float c1, float c2,
+                       bf16 *__restrict__ wb) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        w[i] = wi;
+        if (wb) wb[i] = (bf16)wi;
+    }
+}
+
+__global__ void k_to_bf16(const float *__restrict__ a, long long n, bf16 *__restrict__ out) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        out[i] = (bf16)a[i];
+}
+
+// network input: per voxel the six tensor entries of its phase (feat[phase][6])
+// and the coordinate along x, (x + 1/2) / W - 1/2; channel 7 is zero
+__global__ void k_features(const uint8_t *__restrict__ phase, int D, int H, int W, const float *__restrict__ feat,
+                           bf16 *__restrict__ out) {
+    const long long total = (long long)D * H * W;
+    for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < total; v += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(v % W);
+        const float *f = feat + 6 * phase[v];
+        bf16 *o = out + v * 8;
+        for (int c = 0; c < 6; c++) o[c] = (bf16)f[c];
+        o[6] = (bf16)(((float)x + 0.5f) / (float)W - 0.5f);
+        o[7] = (bf16)0.0f;
+    }
+}
+
+// training target: scale * (T - T_lin(x)), T_lin = 1 - (x + 1/2) / W (walls 1 -> 0)
+__global__ void k_target(const float *__restrict__ T, int D, int H, int W, float scale, float *__restrict__ out) {
+    const long long total = (long long)D * H * W;
+    for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < total; v += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(v % W);
+        out[v] = scale * (T[v] - (1.0f - ((float)x + 0.5f) / (float)W));
+    }
+}
+
+// Temperature start field from a prediction on a grid f times coarser per
+// axis (pred[v][cpred], channel 0 = scale * (T - T_lin)): trilinear
+// interpolation between coarse voxel centres (periodic in y and z, clamped
+// in x), then T = T_lin(x) + pred / scale.  bad[0] counts values that are not
+// finite or outside [-margin, 1 + margin].
+__global__ void k_to_temperature(const float *__restrict__ pred, int cpred, int Dc, int Hc, int Wc, int f, float scale,
+                                 float margin, float *__restrict__ T, int *__restrict__ bad) {
+    const int D = Dc * f, H = Hc * f, W = Wc * f;
+    const long long total = (long long)D * H * W;
+    int nbad = 0;
+    for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < total; v += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(v % W);
+        const long long r = v / W;
+        const int y = (int)(r % H), z = (int)(r / H);
+        // fine voxel centre in coarse-voxel-centre coordinates
+        const float cx = ((float)x + 0.5f) / f - 0.5f, cy = ((float)y + 0.5f) / f - 0.5f, cz = ((float)z + 0.5f) / f - 0.5f;
+        const float fx = floorf(cx), fy = floorf(cy), fz = floorf(cz);
+        const float tx = cx - fx, ty = cy - fy, tz = cz - fz;
+        float acc = 0.0f;
+        for (int dz = 0; dz < 2; dz++)
+            for (int dy = 0; dy < 2; dy++)
+                for (int dx = 0; dx < 2; dx++) {
+                    int ix = (int)fx + dx, iy = (int)fy + dy, iz = (int)fz + dz;
+                    ix = min(max(ix, 0), Wc - 1);
+                    iy = ((iy % Hc) + Hc) % Hc;
+                    iz = ((iz % Dc) + Dc) % Dc;
+                    const float wgt = (dx ? tx : 1.0f - tx) * (dy ? ty : 1.0f - ty) * (dz ? tz : 1.0f - tz);
+                    acc += wgt * pred[(((long long)iz * Hc + iy) * Wc + ix) * cpred];
+                }
+        const float t = (1.0f - ((float)x + 0.5f) / (float)W) + acc / scale;
+        T[v] = t;
+        if (!(t >= -margin && t <= 1.0f + margin)) nbad++;
+    }
+    // per-thread counts summed on the host side through a block reduction
+    __shared__ int red[256];
+    red[threadIdx.x] = nbad;
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bad[blockIdx.x] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+static inline int g1(long long n) {
+    long long b = (n + 255) / 256;
+    return (int)(b > 16384 ? 16384 : (b < 1 ? 1 : b));
+}
+
+hipError_t nn_conv_fwd(const void *in, const void *w, const float *bias, const ConvGeom &g, int relu, void *out,
+                       float *out_f32, hipStream_t s) {
+    const long long nvox = (long long)g.n * g.D * g.H * g.W;
+    const long long vtiles = (nvox + 31) / 32;  // MT = 2
+    const int nt = (g.cout % 64 == 0) ? 4 : ((g.cout % 32 == 0) ? 2 : 1);
+    const dim3 grid((unsigned)((vtiles + 3) / 4), g.cout / (16 * nt)), block(256);
+    const bf16 *i = (const bf16 *)in;
+    const bf16 *ww = (const bf16 *)w;
+    bf16 *o = (bf16 *)out;
+    if (nt == 4) hipLaunchKernelGGL((k_conv_fwd<2, 4>), grid, block, 0, s, i, ww, bias, g, relu, o, out_f32);
+    else if (nt == 2) hipLaunchKernelGGL((k_conv_fwd<2, 2>), grid, block, 0, s, i, ww, bias, g, relu, o, out_f32);
+    else hipLaunchKernelGGL((k_conv_fwd<2, 1>), grid, block, 0, s, i, ww, bias, g, relu, o, out_f32);
+    return hipGetLastError();
+}
+
+hipError_t nn_weight_flip(const void *w, int cin, int cout, int kpad, int kpad_t, void *wt, hipStream_t s) {
+    hipLaunchKernelGGL(k_weight_flip, dim3(g1((long long)cin * kpad_t)), dim3(256), 0, s, (const bf16 *)w, cin, cout,
+                       kpad, kpad_t, (bf16 *)wt);
+    return hipGetLastError();
+}
+
+int nn_wgrad_splits(const ConvGeom &g) {
+    const long long nvox = (long long)g.n * g.D * g.H * g.W;
+    const long long tiles = (long long)(g.kpad / 32) * (g.cout / 16);
+    long long s = (4096 + tiles - 1) / tiles;
+    const long long maxs = (nvox + 31) / 32;
+    if (s > maxs) s = maxs;
+    if (s > 1024) s = 1024;
+    return (int)(s < 1 ? 1 : s);
+}
+
+hipError_t nn_conv_wgrad(const void *x, const void *dy, const ConvGeom &g, int splits, float *partials, float *dw,
+                         hipStream_t s) {
+    const long long nvox = (long long)g.n * g.D * g.H * g.W;
+    long long per = (nvox + splits - 1) / splits;
+    per = (per + 31) / 32 * 32;
+    const dim3 grid(g.kpad / 32, g.cout / 16, splits);
+    hipLaunchKernelGGL(k_conv_wgrad, grid, dim3(64), 0, s, (const bf16 *)x, (const bf16 *)dy, g, per, partials);
+    const long long len = (long long)g.cout * g.kpad;
+    hipLaunchKernelGGL(k_sum_splits, dim3(g1(len)), dim3(256), 0, s, partials, len, splits, dw);
+    return hipGetLastError();
+}
+
+hipError_t nn_bias_grad(const void *dy, long long nvox, int c, int splits, float *partials, float *db, hipStream_t s) {
+    long long per = (nvox + splits - 1) / splits;
+    hipLaunchKernelGGL(k_bias_grad, dim3(splits), dim3(128), 0, s, (const bf16 *)dy, nvox, c, per, partials);
+    hipLaunchKernelGGL(k_sum_splits, dim3(1), dim3(256), 0, s, partials, (long long)c, splits, db);
+    return hipGetLastError();
+}
+
+hipError_t nn_relu_bwd(const void *y, const void *dy, void *dx, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_relu_bwd, dim3(g1(n)), dim3(256), 0, s, (const bf16 *)y, (const bf16 *)dy, (bf16 *)dx, n);
+    return hipGetLastError();
+}
+
+hipError_t nn_add(const void *a, const void *b, void *out, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_add, dim3(g1(n)), dim3(256), 0, s, (const bf16 *)a, (const bf16 *)b, (bf16 *)out, n);
+    return hipGetLastError();
+}
+
+hipError_t nn_pool2(int fwd, const void *in, int n, int D, int H, int W, int c, void *out, hipStream_t s) {
+    const long long big = (long long)n * D * H * W * c;
+    if (fwd) hipLaunchKernelGGL(k_pool2_fwd, dim3(g1(big / 8)), dim3(256), 0, s, (const bf16 *)in, n, D, H, W, c, (bf16 *)out);
+    else hipLaunchKernelGGL(k_pool2_bwd, dim3(g1(big)), dim3(256), 0, s, (const bf16 *)in, n, D, H, W, c, (bf16 *)out);
+    return hipGetLastError();
+}
+
+hipError_t nn_up2(int fwd, const void *in, int n, int D, int H, int W, int c, void *out, hipStream_t s) {
+    const long long small = (long long)n * D * H * W * c;
+    if (fwd) hipLaunchKernelGGL(k_up2_fwd, dim3(g1(small * 8)), dim3(256), 0, s, (const bf16 *)in, n, D, H, W, c, (bf16 *)out);
+    else hipLaunchKernelGGL(k_up2_bwd, dim3(g1(small)), dim3(256), 0, s, (const bf16 *)in, n, D, H, W, c, (bf16 *)out);
+    return hipGetLastError();
+}
+
+hipError_t nn_sum_rows(const float *p, int rows, float scale, float *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(64), 0, s, p, rows, scale, out);
+    return hipGetLastError();
+}
+
+int nn_mse_blocks(long long nvox) { return g1(nvox) > 1024 ? 1024 : g1(nvox); }
+
+hipError_t nn_mse(const float *pred, int cpred, const float *target, long long nvox, void *dpred, float *partials,
+                  hipStream_t s) {
+    hipLaunchKernelGGL(k_mse, dim3(nn_mse_blocks(nvox)), dim3(256), 0, s, pred, cpred, target, nvox, (bf16 *)dpred,
+                       partials);
+    return hipGetLastError();
+}
+
+hipError_t nn_adam(float *w, const float *g, float *m, float *v, long long n, float lr, float b1, float b2, float eps,
+                   int t, void *wb, hipStream_t s) {
+    float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);
+    hipLaunchKernelGGL(k_adam, dim3(g1(n)), dim3(256), 0, s, w, g, m, v, n, lr, b1, b2, eps, c1, c2, (bf16 *)wb);
+    return hipGetLastError();
+}
+
+hipError_t nn_to_bf16(const float *a, long long n, void *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_bf16, dim3(g1(n)), dim3(256), 0, s, a, n, (bf16 *)out);
+    return hipGetLastError();
+}
+
+hipError_t nn_features(const uint8_t *phase, int D, int H, int W, const float *feat, void *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_features, dim3(g1((long long)D * H * W)), dim3(256), 0, s, phase, D, H, W, feat, (bf16 *)out);
+    return hipGetLastError();
+}
+
+hipError_t nn_target(const float *T, int D, int H, int W, float scale, float *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_target, dim3(g1((long long)D * H * W)), dim3(256), 0, s, T, D, H, W, scale, out);
+    return hipGetLastError();
+}
+
+int nn_temp_blocks(long long n) { return g1(n) > 2048 ? 2048 : g1(n); }
+
+hipError_t nn_to_temperature(const float *pred, int cpred, int Dc, int Hc, int Wc, int f, float scale, float margin,
+                             float *T, int *bad, hipStream_t s) {
+    const long long n = (long long)Dc * Hc * Wc * f * f * f;
+    hipLaunchKernelGGL(k_to_temperature, dim3(nn_temp_blocks(n)), dim3(256), 0, s, pred, cpred, Dc, Hc, Wc, f, scale,
+                       margin, T, bad);
+    return hipGetLastError();
+}
+
+}  // namespace mrt

@@ -1,0 +1,510 @@
+"""Learned warm start for the lattice Boltzmann solver.
+
+A 3-D convolutional encoder-decoder (four resolution levels, skip additions,
+~1.3 M parameters) maps a voxel medium -- per voxel the six conductivity-
+tensor entries of its phase and the coordinate along the gradient axis -- to
+the steady temperature's deviation from the linear wall-to-wall profile.  The
+solver then starts from that field (with the matching non-equilibrium flux
+part) instead of from zero; it still iterates to its own stop rule, so the
+network only changes how many steps that takes, never the answer.
+
+Every layer -- BF16 implicit-GEMM convolutions on the matrix cores with FP32
+accumulation, their input and weight gradients, pooling, upsampling, the loss
+and Adam -- runs in the HIP library (include/mrtlbm_nn.h); this module only
+allocates buffers with torch, orders the calls and keeps the training loop.
+
+Media are canonicalised so that the gradient runs along x: a solve along z
+is the x-solve of the medium with x and z exchanged (the lattice is exactly
+symmetric under axis permutations).  The x axis is zero-padded (walls), y and
+z wrap (periodic cell sides).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import time
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, load
+
+CIRC = 0b110  # y and z periodic, x walls
+SCALE = 10.0  # target = SCALE * (T - T_lin)
+MARGIN = 0.05  # a start field outside [T_cold - MARGIN, T_hot + MARGIN] is rejected
+
+# (name, cin, cout, relu)
+LAYERS = [
+    ("c00", 8, 16, True), ("c01", 16, 16, True),
+    ("c10", 16, 32, True), ("c11", 32, 32, True),
+    ("c20", 32, 64, True), ("c21", 64, 64, True),
+    ("c30", 64, 128, True), ("c31", 128, 128, True),
+    ("c22", 128, 64, True), ("c23", 64, 64, True),
+    ("c12", 64, 32, True), ("c13", 32, 32, True),
+    ("c02", 32, 16, True), ("c03", 16, 16, True),
+    ("c04", 16, 16, False),
+]
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def canonical_media(m):
+    """(x-solve medium, z-solve medium) of a cell, both with the gradient along x."""
+    return m, m.permuted((2, 1, 0))
+
+
+def feature_table(k6: np.ndarray) -> np.ndarray:
+    """Per-phase input features: the tensor entries over the largest eigenvalue."""
+    kmax = max(np.linalg.eigvalsh(np.array([[r[0], r[3], r[4]], [r[3], r[1], r[5]], [r[4], r[5], r[2]]])).max()
+               for r in k6)
+    return (np.asarray(k6, np.float64) / kmax).astype(np.float32)
+
+
+class Net:
+    def __init__(self, n: int = 64, batch: int = 4, seed: int = 0, device="cuda:0"):
+        L = load()
+        self.L = L
+        self.dev = torch.device(device)
+        self.n = n
+        self.batch = batch
+        self.stream = torch.cuda.current_stream(self.dev).cuda_stream
+        rng = np.random.default_rng(seed)
+        self.w32, self.b32, self.wbf, self.gw, self.gb, self.mw, self.vw, self.mb, self.vb = ({} for _ in range(9))
+        for name, cin, cout, relu in LAYERS:
+            kpad = L.mrtlbm_nn_kpad(cin)
+            w = np.zeros((cout, kpad), np.float32)
+            std = np.sqrt(2.0 / (27 * cin)) if relu else np.sqrt(1.0 / (27 * cin))
+            if name == "c04":
+                std *= 0.1  # start close to the linear profile
+            w[:, :27 * cin] = rng.standard_normal((cout, 27 * cin)).astype(np.float32) * std
+            self.w32[name] = torch.from_numpy(w).to(self.dev)
+            self.b32[name] = torch.zeros(cout, dtype=torch.float32, device=self.dev)
+            self.wbf[name] = torch.empty((cout, kpad), dtype=torch.bfloat16, device=self.dev)
+            check(L.mrtlbm_nn_to_bf16(_p(self.w32[name]), w.size, _p(self.wbf[name]), self.stream))
+            self.gw[name] = torch.zeros_like(self.w32[name])
+            self.gb[name] = torch.zeros_like(self.b32[name])
+            for d, ref in ((self.mw, self.w32), (self.vw, self.w32), (self.mb, self.b32), (self.vb, self.b32)):
+                d[name] = torch.zeros_like(ref[name])
+        self.t = 0
+        self._alloc(batch)
+
+    # -- buffers -------------------------------------------------------------
+    def _alloc(self, batch):
+        n, dev, bf = self.n, self.dev, torch.bfloat16
+        self.batch = batch
+        vox = [batch * (n >> lv) ** 3 for lv in range(4)]
+        shape = {}
+        # forward activations (channels-last, flattened voxels)
+        for key, lv, c in (("x", 0, 8), ("a00", 0, 16), ("e0", 0, 16), ("p1", 1, 16), ("a10", 1, 32), ("e1", 1, 32),
+                           ("p2", 2, 32), ("a20", 2, 64), ("e2", 2, 64), ("p3", 3, 64), ("a30", 3, 128),
+                           ("e3", 3, 128), ("u2", 2, 128), ("b2", 2, 64), ("s2", 2, 64), ("d2", 2, 64),
+                           ("u1", 1, 64), ("b1", 1, 32), ("s1", 1, 32), ("d1", 1, 32), ("u0", 0, 32),
+                           ("b0", 0, 16), ("s0", 0, 16), ("d0", 0, 16), ("dout", 0, 16)):
+            shape[key] = (vox[lv], c)
+        self.act = {k: torch.empty(v, dtype=bf, device=dev) for k, v in shape.items()}
+        # gradient buffers, one per activation shape class
+        self.grad = {k: torch.empty(v, dtype=bf, device=dev) for k, v in shape.items()}
+        self.tmp = {lv: torch.empty((vox[lv], 128), dtype=bf, device=dev) for lv in range(4)}
+        self.out = torch.empty((vox[0], 16), dtype=torch.float32, device=dev)
+        self.target = torch.empty(vox[0], dtype=torch.float32, device=dev)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.mse_scratch = torch.empty(1024, dtype=torch.float32, device=dev)
+        wt = max(cin * self.L.mrtlbm_nn_kpad(cout) for _, cin, cout, _ in LAYERS)
+        self.wt = torch.empty(wt, dtype=bf, device=dev)
+        ws = 0
+        for _, cin, cout, _ in LAYERS:
+            for lv in range(4):
+                d = n >> lv
+                ws = max(ws, self.L.mrtlbm_nn_wgrad_scratch_bytes(batch, d, d, d, cin, cout))
+        self.wscratch = torch.empty(ws // 4 + 1, dtype=torch.float32, device=dev)
+
+    # -- layer calls -------------------------------------------------------------
+    def _dims(self, lv):
+        d = self.n >> lv
+        return self.batch, d, d, d
+
+    def _conv(self, name, src, dst, lv, out_f32=None):
+        _, cin, cout, relu = next(l for l in LAYERS if l[0] == name)
+        b, d, h, w = self._dims(lv)
+        check(self.L.mrtlbm_nn_conv3d_fwd(_p(src), b, d, h, w, cin, _p(self.wbf[name]), _p(self.b32[name]), cout,
+                                          CIRC, int(relu), _p(dst) if out_f32 is None else None,
+                                          _p(out_f32), self.stream))
+
+    def _pool(self, src, dst, lv_fine, c):
+        b, d, h, w = self._dims(lv_fine)
+        check(self.L.mrtlbm_nn_pool2(1, _p(src), b, d, h, w, c, _p(dst), self.stream))
+
+    def _up(self, src, dst, lv_coarse, c):
+        b, d, h, w = self._dims(lv_coarse)
+        check(self.L.mrtlbm_nn_up2(1, _p(src), b, d, h, w, c, _p(dst), self.stream))
+
+    def _add(self, a, b, out):
+        check(self.L.mrtlbm_nn_add(_p(a), _p(b), _p(out), a.numel(), self.stream))
+
+    def forward(self):
+        A = self.act
+        self._conv("c00", A["x"], A["a00"], 0)
+        self._conv("c01", A["a00"], A["e0"], 0)
+        self._pool(A["e0"], A["p1"], 0, 16)
+        self._conv("c10", A["p1"], A["a10"], 1)
+        self._conv("c11", A["a10"], A["e1"], 1)
+        self._pool(A["e1"], A["p2"], 1, 32)
+        self._conv("c20", A["p2"], A["a20"], 2)
+        self._conv("c21", A["a20"], A["e2"], 2)
+        self._pool(A["e2"], A["p3"], 2, 64)
+        self._conv("c30", A["p3"], A["a30"], 3)
+        self._conv("c31", A["a30"], A["e3"], 3)
+        self._up(A["e3"], A["u2"], 3, 128)
+        self._conv("c22", A["u2"], A["b2"], 2)
+        self._add(A["b2"], A["e2"], A["s2"])
+        self._conv("c23", A["s2"], A["d2"], 2)
+        self._up(A["d2"], A["u1"], 2, 64)
+        self._conv("c12", A["u1"], A["b1"], 1)
+        self._add(A["b1"], A["e1"], A["s1"])
+        self._conv("c13", A["s1"], A["d1"], 1)
+        self._up(A["d1"], A["u0"], 1, 32)
+        self._conv("c02", A["u0"], A["b0"], 0)
+        self._add(A["b0"], A["e0"], A["s0"])
+        self._conv("c03", A["s0"], A["d0"], 0)
+        self._conv("c04", A["d0"], None, 0, out_f32=self.out)
+        return self.out
+
+    def _wgrad(self, name, x, dy, lv):
+        _, cin, cout, _ = next(l for l in LAYERS if l[0] == name)
+        b, d, h, w = self._dims(lv)
+        check(self.L.mrtlbm_nn_conv3d_wgrad(_p(x), _p(dy), b, d, h, w, cin, cout, CIRC, _p(self.wscratch),
+                                            _p(self.gw[name]), _p(self.gb[name]), self.stream))
+
+    def _dgrad(self, name, dy, dx, lv):
+        _, cin, cout, _ = next(l for l in LAYERS if l[0] == name)
+        b, d, h, w = self._dims(lv)
+        check(self.L.mrtlbm_nn_conv3d_dgrad(_p(dy), b, d, h, w, cin, _p(self.wbf[name]), cout, CIRC, _p(self.wt),
+                                            _p(dx), self.stream))
+
+    def _relu_bwd(self, y, dy, dx):
+        check(self.L.mrtlbm_nn_relu_bwd(_p(y), _p(dy), _p(dx), y.numel(), self.stream))
+
+    def _block_bwd(self, name, x, y, dy, lv, dx):
+        """Backward of y = relu(conv(x)): weight grads, and dx if wanted."""
+        t = self.tmp[lv].view(-1)[: y.numel()].view(y.shape)
+        self._relu_bwd(y, dy, t)
+        self._wgrad(name, x, t, lv)
+        if dx is not None:
+            self._dgrad(name, t, dx, lv)
+
+    def backward(self):
+        A, G = self.act, self.grad
+        # head (no activation): dout holds dL/d(out) in BF16
+        self._wgrad("c04", A["d0"], A["dout"], 0)
+        self._dgrad("c04", A["dout"], G["d0"], 0)
+        self._block_bwd("c03", A["s0"], A["d0"], G["d0"], 0, G["s0"])
+        self._block_bwd("c02", A["u0"], A["b0"], G["s0"], 0, G["u0"])
+        b, d, h, w = self._dims(1)
+        check(self.L.mrtlbm_nn_up2(0, _p(G["u0"]), b, d, h, w, 32, _p(G["d1"]), self.stream))
+        self._block_bwd("c13", A["s1"], A["d1"], G["d1"], 1, G["s1"])
+        self._block_bwd("c12", A["u1"], A["b1"], G["s1"], 1, G["u1"])
+        b, d, h, w = self._dims(2)
+        check(self.L.mrtlbm_nn_up2(0, _p(G["u1"]), b, d, h, w, 64, _p(G["d2"]), self.stream))
+        self._block_bwd("c23", A["s2"], A["d2"], G["d2"], 2, G["s2"])
+        self._block_bwd("c22", A["u2"], A["b2"], G["s2"], 2, G["u2"])
+        b, d, h, w = self._dims(3)
+        check(self.L.mrtlbm_nn_up2(0, _p(G["u2"]), b, d, h, w, 128, _p(G["e3"]), self.stream))
+        self._block_bwd("c31", A["a30"], A["e3"], G["e3"], 3, G["a30"])
+        self._block_bwd("c30", A["p3"], A["a30"], G["a30"], 3, G["p3"])
+        # e2 receives the pooled path and the skip from s2
+        b, d, h, w = self._dims(2)
+        check(self.L.mrtlbm_nn_pool2(0, _p(G["p3"]), b, d, h, w, 64, _p(G["e2"]), self.stream))
+        self._add(G["e2"], G["s2"], G["e2"])
+        self._block_bwd("c21", A["a20"], A["e2"], G["e2"], 2, G["a20"])
+        self._block_bwd("c20", A["p2"], A["a20"], G["a20"], 2, G["p2"])
+        b, d, h, w = self._dims(1)
+        check(self.L.mrtlbm_nn_pool2(0, _p(G["p2"]), b, d, h, w, 32, _p(G["e1"]), self.stream))
+        self._add(G["e1"], G["s1"], G["e1"])
+        self._block_bwd("c11", A["a10"], A["e1"], G["e1"], 1, G["a10"])
+        self._block_bwd("c10", A["p1"], A["a10"], G["a10"], 1, G["p1"])
+        b, d, h, w = self._dims(0)
+        check(self.L.mrtlbm_nn_pool2(0, _p(G["p1"]), b, d, h, w, 16, _p(G["e0"]), self.stream))
+        self._add(G["e0"], G["s0"], G["e0"])
+        self._block_bwd("c01", A["a00"], A["e0"], G["e0"], 0, G["a00"])
+        self._block_bwd("c00", A["x"], A["a00"], G["a00"], 0, None)
+
+    def loss_and_grad(self):
+        nvox = self.target.numel()
+        check(self.L.mrtlbm_nn_mse(_p(self.out), 16, _p(self.target), nvox, _p(self.act["dout"]),
+                                   _p(self.mse_scratch), _p(self.loss), self.stream))
+
+    def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.t += 1
+        for name, _, _, _ in LAYERS:
+            check(self.L.mrtlbm_nn_adam(_p(self.w32[name]), _p(self.gw[name]), _p(self.mw[name]), _p(self.vw[name]),
+                                        self.w32[name].numel(), lr, b1, b2, eps, self.t, _p(self.wbf[name]),
+                                        self.stream))
+            check(self.L.mrtlbm_nn_adam(_p(self.b32[name]), _p(self.gb[name]), _p(self.mb[name]), _p(self.vb[name]),
+                                        self.b32[name].numel(), lr, b1, b2, eps, self.t, None, self.stream))
+
+    def set_input(self, b: int, phase_dev: torch.Tensor, feat_dev: torch.Tensor):
+        n = self.n
+        dst = self.act["x"][b * n ** 3:(b + 1) * n ** 3]
+        check(self.L.mrtlbm_nn_features(_p(phase_dev), n, n, n, _p(feat_dev), _p(dst), self.stream))
+
+    # -- persistence -----------------------------------------------------------
+    def state_dict(self):
+        return {"w": {k: v.cpu() for k, v in self.w32.items()}, "b": {k: v.cpu() for k, v in self.b32.items()},
+                "n": self.n, "t": self.t}
+
+    def load_state_dict(self, sd):
+        for name, _, _, _ in LAYERS:
+            self.w32[name].copy_(sd["w"][name].to(self.dev))
+            self.b32[name].copy_(sd["b"][name].to(self.dev))
+            check(self.L.mrtlbm_nn_to_bf16(_p(self.w32[name]), self.w32[name].numel(), _p(self.wbf[name]),
+                                           self.stream))
+        self.t = int(sd.get("t", 0))
+
+    def save(self, path):
+        torch.save(self.state_dict(), path)
+
+    @classmethod
+    def from_file(cls, path, batch=1, device="cuda:0"):
+        sd = torch.load(path, map_location="cpu", weights_only=True)
+        net = cls(n=int(sd["n"]), batch=batch, device=device)
+        net.load_state_dict(sd)
+        return net
+
+
+# ---------------------------------------------------------------------------
+# data, training, inference
+# ---------------------------------------------------------------------------
+
+
+def _gen_braid(spec):
+    import workloads
+
+    m = workloads.braid(spec["nx"], spec["ny"], spec["nz"], spec["gamma"], spec["v"])
+    return m.phase, m.k
+
+
+def generate_media(specs, workers: int = 8):
+    """Voxelise braided cells on the CPU, in worker processes.  Call it before
+    the process first touches the GPU: the workers are forked copies."""
+    import workloads
+
+    if workers <= 1:
+        return [workloads.braid(s["nx"], s["ny"], s["nz"], s["gamma"], s["v"]) for s in specs]
+    from concurrent.futures import ProcessPoolExecutor
+
+    with ProcessPoolExecutor(workers) as ex:
+        out = list(ex.map(_gen_braid, specs, chunksize=4))
+    return [workloads.Medium(p, k) for p, k in out]
+
+
+def linear_start(shape, device, dtype=torch.float32):
+    """T_lin = 1 - (x + 1/2) / nx on a (nz, ny, nx) grid (walls 1 -> 0)."""
+    nx = shape[2]
+    x = (torch.arange(nx, dtype=torch.float64) + 0.5) / nx
+    return (1.0 - x).to(dtype).view(1, 1, nx).expand(*shape).contiguous().to(device)
+
+
+def solve_fields(media, tol=1e-4, check_every=1000, max_steps=5_000_000, start="linear", net=None, batch=True):
+    """Steady x-gradient fields of canonical media (FP32, periodic sides).
+
+    start: "zero", "linear" or "learned" (needs net).  Returns (temperature
+    tensors, results, setup seconds)."""
+    from .solver import Medium, batch_solve
+
+    cells = []
+    t0 = time.perf_counter()
+    fallbacks = 0
+    for m in media:
+        g = Medium(m.phase, m.k, precision="f32")
+        g.set_bc(0, 1.0, 0.0, ("periodic",) * 3)
+        if start == "zero":
+            g.init()
+        elif start == "linear":
+            g.init(linear_start(g.shape, g.device), flux=True)
+        else:
+            T0, bad = predict_start(net, m, g)
+            if bad:
+                fallbacks += 1
+                g.init()
+            else:
+                g.init(T0, flux=True)
+        cells.append(g)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    if batch:
+        res, _ = batch_solve(cells, tol=tol, kind="keff", max_steps=max_steps, check_every=check_every)
+    else:
+        res = [g.solve(tol, "keff", max_steps, check_every=check_every) for g in cells]
+    temps = [g.temperature() for g in cells]
+    return temps, res, setup, fallbacks
+
+
+def predict_start(net: Net, m, g) -> tuple[torch.Tensor, int]:
+    """Network start field for medium m on solver medium g (x gradient).
+    Cells larger than the network's grid are averaged down by 2x steps, the
+    prediction is interpolated back.  Returns (T0, number of rejected values)."""
+    L = net.L
+    n = net.n
+    nz, ny, nx = m.phase.shape
+    f = nx // n
+    assert nx == ny == nz == n * f and f in (1, 2, 4), "cubic cells of n * {1, 2, 4} voxels"
+    s = net.stream
+    feat = torch.from_numpy(feature_table(m.k)).to(net.dev)
+    phase = g.phase
+    if f == 1:
+        net.set_input(0, phase, feat)
+    else:
+        big = torch.empty((nx ** 3, 8), dtype=torch.bfloat16, device=net.dev)
+        check(L.mrtlbm_nn_features(_p(phase), nx, nx, nx, _p(feat), _p(big), s))
+        cur, size = big, nx
+        while size > n:
+            nxt = torch.empty(((size // 2) ** 3, 8), dtype=torch.bfloat16, device=net.dev) if size // 2 > n \
+                else net.act["x"][: n ** 3]
+            check(L.mrtlbm_nn_pool2(1, _p(cur), 1, size, size, size, 8, _p(nxt), s))
+            cur, size = nxt, size // 2
+    net.forward()
+    T0 = torch.empty((nx, nx, nx), dtype=torch.float32, device=net.dev)
+    bad_scratch = torch.empty(2048, dtype=torch.int32, device=net.dev)
+    bad = ctypes.c_longlong()
+    check(L.mrtlbm_nn_to_temperature(_p(net.out), 16, n, n, n, f, SCALE, MARGIN, _p(T0), _p(bad_scratch),
+                                     ctypes.byref(bad), s))
+    return T0, bad.value
+
+
+def make_dataset(media, size=64, tol=1e-4, chunk=128, log=print):
+    """Steady fields of braided cells (already voxelised); each cell gives two
+    samples (x- and z-solve, canonicalised).  Returns device tensors (phases
+    uint8 [S, size^3], feature tables [S, nphase, 6], targets [S, size^3])
+    and statistics."""
+    canon = [mm for m in media for mm in canonical_media(m)]
+    phases, feats, targets = [], [], []
+    steps = []
+    t0 = time.perf_counter()
+    for c0 in range(0, len(canon), chunk):
+        part = canon[c0:c0 + chunk]
+        temps, res, _, _ = solve_fields(part, tol=tol, start="linear")
+        for m, T, r in zip(part, temps, res):
+            tgt = torch.empty(size ** 3, dtype=torch.float32, device=T.device)
+            check(load().mrtlbm_nn_target(_p(T), size, size, size, SCALE, _p(tgt),
+                                          torch.cuda.current_stream().cuda_stream))
+            phases.append(torch.from_numpy(m.phase.reshape(-1)).to(T.device))
+            feats.append(torch.from_numpy(feature_table(m.k)).to(T.device))
+            targets.append(tgt)
+            steps.append(r["steps"])
+        log(f"dataset: {min(c0 + chunk, len(canon))}/{len(canon)} fields, {time.perf_counter() - t0:.1f} s")
+    return (torch.stack(phases), torch.stack(feats), torch.stack(targets)), dict(
+        seconds=time.perf_counter() - t0, mean_steps=float(np.mean(steps)))
+
+
+def train(net: Net, data, iters=2000, lr=1e-3, seed=0, log=print, log_every=100):
+    phases, feats, targets = data
+    S = phases.shape[0]
+    rng = np.random.default_rng(seed)
+    nv = net.n ** 3
+    losses = []
+    t0 = time.perf_counter()
+    for it in range(1, iters + 1):
+        idx = rng.choice(S, size=net.batch, replace=False)
+        for b, i in enumerate(idx):
+            net.set_input(b, phases[i], feats[i])
+            net.target[b * nv:(b + 1) * nv].copy_(targets[i])
+        net.forward()
+        net.loss_and_grad()
+        net.backward()
+        cur_lr = lr * (0.1 ** (it / iters))  # exponential decay to lr / 10
+        net.adam(lr=cur_lr)
+        if it % log_every == 0 or it == iters:
+            loss = float(net.loss.item())
+            losses.append((it, loss))
+            log(f"train it {it}: loss {loss:.3e}  ({time.perf_counter() - t0:.1f} s)")
+    return losses
+
+
+def evaluate(net: Net, data) -> float:
+    phases, feats, targets = data
+    nv = net.n ** 3
+    tot = 0.0
+    S = phases.shape[0]
+    for i0 in range(0, S - S % net.batch, net.batch):
+        for b in range(net.batch):
+            net.set_input(b, phases[i0 + b], feats[i0 + b])
+            net.target[b * nv:(b + 1) * nv].copy_(targets[i0 + b])
+        net.forward()
+        net.loss_and_grad()
+        tot += float(net.loss.item())
+    return tot / max(1, S // net.batch)
+
+
+def bench(args) -> dict:
+    """Held-out cells solved from zero, linear and learned starts (same stop
+    rule, FP32, periodic sides, x and z solves)."""
+    import workloads
+
+    specs = workloads.warmstart_cells(args.seed if args.seed != 1503 else 8719, args.cells, args.n)
+    t_gen = time.perf_counter()
+    media = generate_media(specs)
+    canon = [mm for m in media for mm in canonical_media(m)]
+    t_gen = time.perf_counter() - t_gen
+    net = Net.from_file(args.model, batch=1)
+    out = {"mode": "warmstart", "cells": len(media), "size": args.n, "tol": args.tol, "solves_per_cell": 2,
+           "seconds_geometry": round(t_gen, 2)}
+    ref = None
+    for start in ("zero", "linear", "learned"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        temps, res, setup, fb = solve_fields(canon, tol=args.tol, start=start, net=net, batch=False)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ks = [r["keff"] for r in res]
+        rec = {"steps_mean": float(np.mean([r["steps"] for r in res])),
+               "steps": [r["steps"] for r in res], "seconds": round(wall, 2), "setup_seconds": round(setup, 2),
+               "cells_per_hour": round(len(media) / ((wall + t_gen) / 3600.0), 1), "fallbacks": fb,
+               "all_converged": all(r["converged"] for r in res)}
+        if ref is None:
+            ref = ks
+        rec["max_rel_keff_diff_vs_zero_start"] = float(max(abs(a - b) / abs(b) for a, b in zip(ks, ref)))
+        out[start] = rec
+        print(f"warmstart {start}: mean steps {rec['steps_mean']:.0f}, {wall:.1f} s", flush=True)
+    return out
+
+
+def main():
+    import argparse
+    import json
+
+    p = argparse.ArgumentParser(description="generate data, train and save the warm-start network")
+    p.add_argument("--cells", type=int, default=256)
+    p.add_argument("--val-cells", type=int, default=16)
+    p.add_argument("--size", type=int, default=64)
+    p.add_argument("--iters", type=int, default=3000)
+    p.add_argument("--batch", type=int, default=4)
+    p.add_argument("--lr", type=float, default=1e-3)
+    p.add_argument("--out", default=os.path.join(os.path.dirname(__file__), "warmstart_model.pt"))
+    p.add_argument("--workers", type=int, default=8)
+    a = p.parse_args()
+    import workloads
+
+    # voxelise every cell before the GPU is touched (forked workers)
+    train_media = generate_media(workloads.warmstart_cells(8718, a.cells, a.size), a.workers)
+    val_media = generate_media(workloads.warmstart_cells(8720, a.val_cells, a.size), a.workers)
+    _lib.load()
+    data, st = make_dataset(train_media, a.size)
+    val, _ = make_dataset(val_media, a.size)
+    net = Net(n=a.size, batch=a.batch, seed=0)
+    before = evaluate(net, val)
+    t0 = time.perf_counter()
+    losses = train(net, data, iters=a.iters, lr=a.lr)
+    t_train = time.perf_counter() - t0
+    after = evaluate(net, val)
+    net.save(a.out)
+    print(json.dumps({"train_samples": int(data[0].shape[0]), "data_seconds": round(st["seconds"], 1),
+                      "data_mean_steps": st["mean_steps"], "train_seconds": round(t_train, 1),
+                      "val_loss_before": before, "val_loss_after": after, "losses": losses[-5:], "out": a.out}))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,275 @@
+"""Warm-start network kernels (BF16 MFMA, FP32 accumulation) against the FP64
+reference of oracle/conv.py.
+
+Inputs are drawn, rounded to BF16 on the host, and the same rounded values
+feed both sides, so the differences are the GPU's FP32 accumulation and its
+BF16 outputs.  Bars: relative L2 <= 1e-2 and cosine >= 0.999 for BF16
+outputs, relative L2 <= 1e-4 for FP32 outputs of exact-BF16 inputs.
+"""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import conv as C
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device")
+    from paper_1503_08718_amd import load
+
+    L = load()
+    return L, torch
+
+
+def bf(torch, a):
+    """Round to BF16; return (device tensor, float64 numpy copy of the rounded values)."""
+    t = torch.tensor(np.asarray(a, np.float32)).to(torch.bfloat16)
+    return t.cuda(), t.float().numpy().astype(np.float64)
+
+
+def P(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def cosine(a, b):
+    a, b = np.ravel(a), np.ravel(b)
+    return float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+
+
+def circ_bits(circ):
+    return int(circ[0]) | (int(circ[1]) << 1) | (int(circ[2]) << 2)
+
+
+def pack_w(L, w):
+    """oracle weights [cout, 3, 3, 3, cin] -> GPU rows [cout][kpad]."""
+    cout, cin = w.shape[0], w.shape[-1]
+    kpad = L.mrtlbm_nn_kpad(cin)
+    out = np.zeros((cout, kpad), np.float32)
+    out[:, :27 * cin] = w.reshape(cout, 27 * cin)
+    return out
+
+
+SHAPES = [
+    # (n, D, H, W, cin, cout, circ)
+    (2, 4, 6, 10, 8, 16, (False, True, True)),
+    (1, 8, 8, 8, 16, 32, (True, True, True)),
+    (2, 6, 4, 8, 32, 64, (False, False, False)),
+    (1, 4, 4, 4, 128, 128, (False, True, True)),
+    (1, 6, 10, 4, 64, 16, (True, False, True)),
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s[:6])))
+def test_conv_forward(env, shape):
+    L, torch = env
+    n, D, H, W, cin, cout, circ = shape
+    rng = np.random.default_rng(cin * 7 + cout)
+    xd, x = bf(torch, rng.standard_normal((n, D, H, W, cin)))
+    w = rng.standard_normal((cout, 3, 3, 3, cin)) * 0.2
+    wd, wq = bf(torch, pack_w(L, w))
+    w_or = wq[:, :27 * cin].reshape(cout, 3, 3, 3, cin)
+    b = torch.tensor(rng.standard_normal(cout).astype(np.float32)).cuda()
+    ref = C.conv3d(x, w_or, b.cpu().numpy().astype(np.float64), circ)
+    out32 = torch.empty((n * D * H * W, cout), dtype=torch.float32, device="cuda")
+    assert L.mrtlbm_nn_conv3d_fwd(P(xd), n, D, H, W, cin, P(wd), P(b), cout, circ_bits(circ), 0, None, P(out32),
+                                  None) == 0
+    assert rel_l2(out32.cpu().numpy(), ref) < 1e-5
+    outb = torch.empty((n * D * H * W, cout), dtype=torch.bfloat16, device="cuda")
+    assert L.mrtlbm_nn_conv3d_fwd(P(xd), n, D, H, W, cin, P(wd), P(b), cout, circ_bits(circ), 1, P(outb), None,
+                                  None) == 0
+    got = outb.float().cpu().numpy()
+    r = C.relu(ref)
+    assert rel_l2(got, r) < 1e-2 and cosine(got, r) > 0.999
+
+
+@pytest.mark.parametrize("shape", [s for s in SHAPES if s[4] >= 16], ids=lambda s: "x".join(map(str, s[:6])))
+def test_conv_backward(env, shape):
+    L, torch = env
+    n, D, H, W, cin, cout, circ = shape
+    rng = np.random.default_rng(cin + 3 * cout)
+    xd, x = bf(torch, rng.standard_normal((n, D, H, W, cin)))
+    w = rng.standard_normal((cout, 3, 3, 3, cin)) * 0.2
+    wd, wq = bf(torch, pack_w(L, w))
+    w_or = wq[:, :27 * cin].reshape(cout, 3, 3, 3, cin)
+    dyd, dy = bf(torch, rng.standard_normal((n, D, H, W, cout)))
+    dx_ref, dw_ref, db_ref = C.conv3d_backward(x, w_or, dy, circ)
+    wt = torch.empty(cin * L.mrtlbm_nn_kpad(cout), dtype=torch.bfloat16, device="cuda")
+    dx = torch.empty((n * D * H * W, cin), dtype=torch.bfloat16, device="cuda")
+    assert L.mrtlbm_nn_conv3d_dgrad(P(dyd), n, D, H, W, cin, P(wd), cout, circ_bits(circ), P(wt), P(dx), None) == 0
+    got = dx.float().cpu().numpy()
+    assert rel_l2(got, dx_ref) < 1e-2 and cosine(got, dx_ref) > 0.999
+    nbytes = L.mrtlbm_nn_wgrad_scratch_bytes(n, D, H, W, cin, cout)
+    scratch = torch.empty(nbytes // 4 + 1, dtype=torch.float32, device="cuda")
+    dw = torch.empty((cout, L.mrtlbm_nn_kpad(cin)), dtype=torch.float32, device="cuda")
+    db = torch.empty(cout, dtype=torch.float32, device="cuda")
+    assert L.mrtlbm_nn_conv3d_wgrad(P(xd), P(dyd), n, D, H, W, cin, cout, circ_bits(circ), P(scratch), P(dw), P(db),
+                                    None) == 0
+    dwg = dw.cpu().numpy()
+    assert np.all(dwg[:, 27 * cin:] == 0)
+    assert rel_l2(dwg[:, :27 * cin], dw_ref.reshape(cout, -1)) < 1e-4
+    assert rel_l2(db.cpu().numpy(), db_ref) < 1e-4
+
+
+def test_pool_upsample_add_relu(env):
+    L, torch = env
+    rng = np.random.default_rng(9)
+    n, D, H, W, c = 2, 4, 6, 8, 16
+    xd, x = bf(torch, rng.standard_normal((n, D, H, W, c)))
+    out = torch.empty((n * D * H * W // 8, c), dtype=torch.bfloat16, device="cuda")
+    assert L.mrtlbm_nn_pool2(1, P(xd), n, D, H, W, c, P(out), None) == 0
+    assert rel_l2(out.float().cpu().numpy(), C.pool2(x)) < 5e-3
+    yd, y = bf(torch, rng.standard_normal((n, D // 2, H // 2, W // 2, c)))
+    back = torch.empty((n * D * H * W, c), dtype=torch.bfloat16, device="cuda")
+    assert L.mrtlbm_nn_pool2(0, P(yd), n, D, H, W, c, P(back), None) == 0
+    assert rel_l2(back.float().cpu().numpy(), C.pool2_backward(y)) < 5e-3
+    up = torch.empty((n * D * H * W, c), dtype=torch.bfloat16, device="cuda")
+    assert L.mrtlbm_nn_up2(1, P(yd), n, D // 2, H // 2, W // 2, c, P(up), None) == 0
+    assert np.array_equal(up.float().cpu().numpy().reshape(n, D, H, W, c), C.up2(y))
+    dn = torch.empty((n * D * H * W // 8, c), dtype=torch.bfloat16, device="cuda")
+    assert L.mrtlbm_nn_up2(0, P(xd), n, D // 2, H // 2, W // 2, c, P(dn), None) == 0
+    assert rel_l2(dn.float().cpu().numpy(), C.up2_backward(x)) < 5e-3
+    s = torch.empty_like(xd)
+    assert L.mrtlbm_nn_add(P(xd), P(xd), P(s), xd.numel(), None) == 0
+    assert np.array_equal(s.float().cpu().numpy(), 2 * x)
+    g = torch.empty_like(xd)
+    assert L.mrtlbm_nn_relu_bwd(P(xd), P(xd), P(g), xd.numel(), None) == 0
+    assert np.array_equal(g.float().cpu().numpy(), np.where(x > 0, x, 0))
+
+
+def test_mse_and_adam(env):
+    L, torch = env
+    rng = np.random.default_rng(10)
+    nv = 5000
+    pred = torch.tensor(rng.standard_normal((nv, 16)).astype(np.float32)).cuda()
+    tgt = torch.tensor(rng.standard_normal(nv).astype(np.float32)).cuda()
+    dpred = torch.empty((nv, 16), dtype=torch.bfloat16, device="cuda")
+    scratch = torch.empty(1024, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    assert L.mrtlbm_nn_mse(P(pred), 16, P(tgt), nv, P(dpred), P(scratch), P(loss), None) == 0
+    lref, gref = C.mse(pred.cpu().numpy()[:, 0], tgt.cpu().numpy())
+    assert abs(loss.item() - lref) < 1e-5 * lref
+    d = dpred.float().cpu().numpy()
+    assert rel_l2(d[:, 0], gref) < 5e-3 and np.all(d[:, 1:] == 0)
+    w0 = rng.standard_normal(777)
+    w = torch.tensor(w0.astype(np.float32)).cuda()
+    m = torch.zeros_like(w)
+    v = torch.zeros_like(w)
+    wb = torch.empty(777, dtype=torch.bfloat16, device="cuda")
+    wr, mr, vr = w0.copy(), np.zeros(777), np.zeros(777)
+    for t in range(1, 4):
+        gnp = rng.standard_normal(777)
+        g = torch.tensor(gnp.astype(np.float32)).cuda()
+        assert L.mrtlbm_nn_adam(P(w), P(g), P(m), P(v), 777, 1e-2, 0.9, 0.999, 1e-8, t, P(wb), None) == 0
+        wr, mr, vr = C.adam(wr, gnp.astype(np.float32).astype(np.float64), mr, vr, t, lr=1e-2)
+    assert np.allclose(w.cpu().numpy(), wr, atol=1e-5)
+    assert rel_l2(wb.float().cpu().numpy(), wr) < 5e-3
+
+
+def _oracle_net(x, W, B, target):
+    """FP64 forward/backward of the warm-start network with the same weights."""
+    circ = (False, True, True)
+    f = {}
+
+    def conv(name, inp, relu=True):
+        y = C.conv3d(inp, W[name], B[name], circ)
+        return C.relu(y) if relu else y
+
+    f["a00"] = conv("c00", x)
+    f["e0"] = conv("c01", f["a00"])
+    f["p1"] = C.pool2(f["e0"])
+    f["a10"] = conv("c10", f["p1"])
+    f["e1"] = conv("c11", f["a10"])
+    f["p2"] = C.pool2(f["e1"])
+    f["a20"] = conv("c20", f["p2"])
+    f["e2"] = conv("c21", f["a20"])
+    f["p3"] = C.pool2(f["e2"])
+    f["a30"] = conv("c30", f["p3"])
+    f["e3"] = conv("c31", f["a30"])
+    f["u2"] = C.up2(f["e3"])
+    f["b2"] = conv("c22", f["u2"])
+    f["s2"] = f["b2"] + f["e2"]
+    f["d2"] = conv("c23", f["s2"])
+    f["u1"] = C.up2(f["d2"])
+    f["b1"] = conv("c12", f["u1"])
+    f["s1"] = f["b1"] + f["e1"]
+    f["d1"] = conv("c13", f["s1"])
+    f["u0"] = C.up2(f["d1"])
+    f["b0"] = conv("c02", f["u0"])
+    f["s0"] = f["b0"] + f["e0"]
+    f["d0"] = conv("c03", f["s0"])
+    out = conv("c04", f["d0"], relu=False)
+    loss, dpred = C.mse(out[..., 0].ravel(), target)
+    grads = {}
+
+    def back(name, inp, y, dy, relu=True):
+        dpre = dy * (y > 0) if relu else dy
+        dx, dw, db = C.conv3d_backward(inp, W[name], dpre, circ)
+        grads[name] = (dw, db)
+        return dx
+
+    dout = np.zeros(out.shape)
+    dout[..., 0] = dpred.reshape(out.shape[:-1])
+    g_d0 = back("c04", f["d0"], out, dout, relu=False)
+    g_s0 = back("c03", f["s0"], f["d0"], g_d0)
+    g_u0 = back("c02", f["u0"], f["b0"], g_s0)
+    g_d1 = C.up2_backward(g_u0)
+    g_s1 = back("c13", f["s1"], f["d1"], g_d1)
+    g_u1 = back("c12", f["u1"], f["b1"], g_s1)
+    g_d2 = C.up2_backward(g_u1)
+    g_s2 = back("c23", f["s2"], f["d2"], g_d2)
+    g_u2 = back("c22", f["u2"], f["b2"], g_s2)
+    g_e3 = C.up2_backward(g_u2)
+    g_a30 = back("c31", f["a30"], f["e3"], g_e3)
+    g_p3 = back("c30", f["p3"], f["a30"], g_a30)
+    g_e2 = C.pool2_backward(g_p3) + g_s2
+    g_a20 = back("c21", f["a20"], f["e2"], g_e2)
+    g_p2 = back("c20", f["p2"], f["a20"], g_a20)
+    g_e1 = C.pool2_backward(g_p2) + g_s1
+    g_a10 = back("c11", f["a10"], f["e1"], g_e1)
+    g_p1 = back("c10", f["p1"], f["a10"], g_a10)
+    g_e0 = C.pool2_backward(g_p1) + g_s0
+    g_a00 = back("c01", f["a00"], f["e0"], g_e0)
+    back("c00", x, f["a00"], g_a00)
+    return loss, out, grads
+
+
+def test_whole_network_forward_and_gradients(env):
+    L, torch = env
+    from paper_1503_08718_amd import warmstart as ws
+
+    n = 16
+    net = ws.Net(n=n, batch=1, seed=3)
+    rng = np.random.default_rng(11)
+    xd, x = bf(torch, np.concatenate([rng.uniform(-1, 1, (n ** 3, 7)), np.zeros((n ** 3, 1))], axis=1))
+    net.act["x"].copy_(xd)
+    tgt = rng.uniform(-1, 1, n ** 3).astype(np.float32)
+    net.target.copy_(torch.tensor(tgt).cuda())
+    net.forward()
+    net.loss_and_grad()
+    net.backward()
+    W, B = {}, {}
+    for name, cin, cout, _ in ws.LAYERS:
+        wq = net.wbf[name].float().cpu().numpy().astype(np.float64)
+        W[name] = wq[:, :27 * cin].reshape(cout, 3, 3, 3, cin)
+        B[name] = net.b32[name].cpu().numpy().astype(np.float64)
+    loss, out, grads = _oracle_net(x.reshape(1, n, n, n, 8), W, B, tgt.astype(np.float64))
+    got_out = net.out.cpu().numpy()[:, 0]
+    assert cosine(got_out, out[..., 0].ravel()) > 0.999
+    assert abs(net.loss.item() - loss) < 0.02 * loss
+    for name, cin, cout, _ in ws.LAYERS:
+        gw = net.gw[name].cpu().numpy()[:, :27 * cin]
+        rw = grads[name][0].reshape(cout, -1)
+        assert cosine(gw, rw) > 0.99, name
+        assert rel_l2(gw, rw) < 0.1, name
