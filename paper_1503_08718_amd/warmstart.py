@@ -400,6 +400,19 @@ def make_dataset(media, size=64, tol=1e-4, chunk=128, log=print):
         seconds=time.perf_counter() - t0, mean_steps=float(np.mean(steps)))
 
 
+def iteration_flops(net: Net) -> float:
+    """Matrix-core FLOPs of one training iteration (forward, input and weight
+    gradients; the first layer has no input gradient)."""
+    level = {"c00": 0, "c01": 0, "c10": 1, "c11": 1, "c20": 2, "c21": 2, "c30": 3, "c31": 3, "c22": 2, "c23": 2,
+             "c12": 1, "c13": 1, "c02": 0, "c03": 0, "c04": 0}
+    tot = 0.0
+    for name, cin, cout, _ in LAYERS:
+        vox = net.batch * (net.n >> level[name]) ** 3
+        f = 2.0 * vox * 27 * cin * cout
+        tot += f * (2 if name == "c00" else 3)
+    return tot
+
+
 def train(net: Net, data, iters=2000, lr=1e-3, seed=0, log=print, log_every=100):
     phases, feats, targets = data
     S = phases.shape[0]
@@ -420,7 +433,8 @@ def train(net: Net, data, iters=2000, lr=1e-3, seed=0, log=print, log_every=100)
         if it % log_every == 0 or it == iters:
             loss = float(net.loss.item())
             losses.append((it, loss))
-            log(f"train it {it}: loss {loss:.3e}  ({time.perf_counter() - t0:.1f} s)")
+            dt = time.perf_counter() - t0
+            log(f"train it {it}: loss {loss:.3e}  ({dt:.1f} s, {iteration_flops(net) * it / dt / 1e12:.2f} TFLOP/s)")
     return losses
 
 
@@ -492,6 +506,7 @@ def main():
     train_media = generate_media(workloads.warmstart_cells(8718, a.cells, a.size), a.workers)
     val_media = generate_media(workloads.warmstart_cells(8720, a.val_cells, a.size), a.workers)
     _lib.load()
+    _lib.set_progress(lambda msg: print(msg, flush=True), 30.0)
     data, st = make_dataset(train_media, a.size)
     val, _ = make_dataset(val_media, a.size)
     net = Net(n=a.size, batch=a.batch, seed=0)
@@ -503,6 +518,7 @@ def main():
     net.save(a.out)
     print(json.dumps({"train_samples": int(data[0].shape[0]), "data_seconds": round(st["seconds"], 1),
                       "data_mean_steps": st["mean_steps"], "train_seconds": round(t_train, 1),
+                      "train_tflops": round(iteration_flops(net) * a.iters / t_train / 1e12, 3),
                       "val_loss_before": before, "val_loss_after": after, "losses": losses[-5:], "out": a.out}))
 
 

@@ -1,0 +1,60 @@
+"""Learned warm start: what the trained network gains, and its fallback."""
+
+import os
+
+import numpy as np
+import pytest
+
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+MODEL = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1503_08718_amd",
+                     "warmstart_model.pt")
+
+
+@pytest.fixture(scope="module")
+def ws():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device")
+    from paper_1503_08718_amd import warmstart
+
+    return warmstart
+
+
+def test_learned_start_needs_fewer_steps(ws):
+    assert os.path.exists(MODEL), "trained model missing (python -m paper_1503_08718_amd.warmstart)"
+    media = [w.braid(c["nx"], c["ny"], c["nz"], c["gamma"], c["v"]) for c in w.warmstart_cells(8719, 3, 64)]
+    canon = [mm for m in media for mm in ws.canonical_media(m)]
+    net = ws.Net.from_file(MODEL, batch=1)
+    res = {}
+    for start in ("zero", "linear", "learned"):
+        _, r, _, fb = ws.solve_fields(canon, tol=1e-4, start=start, net=net, batch=False)
+        assert fb == 0 and all(x["converged"] for x in r)
+        res[start] = r
+    zero = np.mean([r["steps"] for r in res["zero"]])
+    learned = np.mean([r["steps"] for r in res["learned"]])
+    print("mean steps to 1e-4: zero", zero, "linear", np.mean([r["steps"] for r in res["linear"]]),
+          "learned", learned)
+    assert learned < zero
+    # the solver, not the network, decides the answer
+    for a, b in zip(res["learned"], res["zero"]):
+        assert abs(a["keff"] - b["keff"]) < 2e-4 * abs(b["keff"])
+
+
+def test_rejected_prediction_falls_back_to_zero_start(ws):
+    import torch
+
+    net = ws.Net(n=16, batch=1, seed=1)
+    net.b32["c04"].fill_(float("nan"))  # a network that predicts NaN everywhere
+    m = w.braid(32, 32, 32, 30.0, 0.5)
+    from paper_1503_08718_amd.solver import Medium
+
+    g = Medium(m.phase, m.k).set_bc(0)
+    T0, bad = ws.predict_start(net, m, g)
+    assert bad == 32 ** 3
+    _, r, _, fb = ws.solve_fields([m], tol=1e-3, start="learned", net=net, batch=False)
+    assert fb == 1 and r[0]["converged"]
+    torch.cuda.synchronize()
