@@ -51,7 +51,8 @@ typedef enum { MRTLBM_F32 = 0, MRTLBM_F64 = 1 } mrtlbm_precision;
 typedef enum { MRTLBM_PERIODIC = 0, MRTLBM_ADIABATIC = 1 } mrtlbm_side;
 typedef enum {
     MRTLBM_TOL_MAXDT = 0, /* stop when max |T(t) - T(t-1)| at a check < tol                        */
-    MRTLBM_TOL_KEFF = 1   /* stop when |k_hot - k_cold + k_leak| / k_mid < tol and k_mid moved < tol/10 */
+    MRTLBM_TOL_KEFF = 1   /* stop when |k_hot - k_cold + k_leak| / k < tol and the last change of k
+                             between checks, with its geometric tail, is < tol/4 */
 } mrtlbm_tol_kind;
 
 typedef struct mrtlbm_medium mrtlbm_medium;

@@ -569,9 +569,25 @@ int mrt::stop_rule(StopState &ss, const mrtlbm_result &r, double tol, mrtlbm_tol
     // energy accumulation rate through the walls plus the exact rounding
     // energy of the stored state: dE/dt of the stored field, relative to the
     // through-flux (equal to the plain wall-flux gap in exact arithmetic)
-    const double km = r.keff;
-    const bool gap_ok = std::fabs(r.keff_hot - r.keff_cold + r.keff_leak) < tol * std::fabs(km);
-    const bool chg_ok = ss.have_prev && std::fabs(km - ss.kprev) < 0.1 * tol * std::fabs(km);
+    const double km = r.keff, ak = std::fabs(km);
+    const bool gap_ok = std::fabs(r.keff_hot - r.keff_cold + r.keff_leak) < tol * ak;
+    // remaining change of k: the last change d between checks, extended by
+    // its geometric tail d r / (1 - r), r = |d| / |previous d| (the slowest
+    // mode decays geometrically); from a zero start T rises monotonically and
+    // the gap alone bounds the error, from any other start this tail does
+    bool chg_ok = false;
+    if (ss.have_prev) {
+        const double d = km - ss.kprev;
+        if (std::fabs(d) < 1e-3 * tol * ak) {
+            chg_ok = true;  // change at round-off level
+        } else if (ss.have_d) {
+            const double ratio = std::fabs(d) / std::max(std::fabs(ss.dprev), 1e-300);
+            const double tail = ratio < 0.999 ? std::fabs(d) * ratio / (1.0 - ratio) : 1e300;
+            chg_ok = std::max(std::fabs(d), tail) < 0.25 * tol * ak;
+        }
+        ss.dprev = d;
+        ss.have_d = true;
+    }
     ss.kprev = km;
     ss.have_prev = true;
     return (gap_ok && chg_ok) ? 1 : 0;

@@ -19,8 +19,8 @@ struct GraphEntry {
 };
 
 struct StopState {
-    double kprev = 0.0;
-    bool have_prev = false;
+    double kprev = 0.0, dprev = 0.0;
+    bool have_prev = false, have_d = false;
     double min_resid = -1.0;
 };
 

@@ -308,18 +308,19 @@ def linear_start(shape, device, dtype=torch.float32):
     return (1.0 - x).to(dtype).view(1, 1, nx).expand(*shape).contiguous().to(device)
 
 
-def solve_fields(media, tol=1e-4, check_every=1000, max_steps=5_000_000, start="linear", net=None, batch=True):
-    """Steady x-gradient fields of canonical media (FP32, periodic sides).
+def solve_fields(media, tol=1e-4, check_every=1000, max_steps=5_000_000, start="linear", net=None, batch=True,
+                 precision="f32"):
+    """Steady x-gradient fields of canonical media (periodic sides).
 
     start: "zero", "linear" or "learned" (needs net).  Returns (temperature
-    tensors, results, setup seconds)."""
+    tensors, results, setup seconds, number of rejected predictions)."""
     from .solver import Medium, batch_solve
 
     cells = []
     t0 = time.perf_counter()
     fallbacks = 0
     for m in media:
-        g = Medium(m.phase, m.k, precision="f32")
+        g = Medium(m.phase, m.k, precision=precision)
         g.set_bc(0, 1.0, 0.0, ("periodic",) * 3)
         if start == "zero":
             g.init()
@@ -331,7 +332,7 @@ def solve_fields(media, tol=1e-4, check_every=1000, max_steps=5_000_000, start="
                 fallbacks += 1
                 g.init()
             else:
-                g.init(T0, flux=True)
+                g.init(T0.to(g.dtype), flux=True)
         cells.append(g)
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
@@ -466,7 +467,13 @@ def bench(args) -> dict:
     net = Net.from_file(args.model, batch=1)
     out = {"mode": "warmstart", "cells": len(media), "size": args.n, "tol": args.tol, "solves_per_cell": 2,
            "seconds_geometry": round(t_gen, 2)}
-    ref = None
+    # reference: FP64, tolerance 100x tighter, from the learned start
+    _, rres, _, _ = solve_fields(canon, tol=args.tol / 100, start="learned", net=net, batch=False,
+                                 precision="f64", max_steps=20_000_000)
+    ref = [r["keff"] for r in rres]
+    out["reference"] = {"precision": "f64", "tol": args.tol / 100, "all_converged": all(r["converged"] for r in rres),
+                        "keff": [round(k, 7) for k in ref]}
+    print("warmstart reference done", flush=True)
     for start in ("zero", "linear", "learned"):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -478,9 +485,9 @@ def bench(args) -> dict:
                "steps": [r["steps"] for r in res], "seconds": round(wall, 2), "setup_seconds": round(setup, 2),
                "cells_per_hour": round(len(media) / ((wall + t_gen) / 3600.0), 1), "fallbacks": fb,
                "all_converged": all(r["converged"] for r in res)}
-        if ref is None:
-            ref = ks
-        rec["max_rel_keff_diff_vs_zero_start"] = float(max(abs(a - b) / abs(b) for a, b in zip(ks, ref)))
+        errs = [abs(a - b) / abs(b) for a, b in zip(ks, ref)]
+        rec["max_rel_err_vs_reference"] = float(max(errs))
+        rec["mean_rel_err_vs_reference"] = float(np.mean(errs))
         out[start] = rec
         print(f"warmstart {start}: mean steps {rec['steps_mean']:.0f}, {wall:.1f} s", flush=True)
     return out
