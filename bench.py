@@ -68,6 +68,8 @@ def parse():
     p.add_argument("--tol", type=float, default=1e-4)
     p.add_argument("--ref-tol", type=float, default=1e-7)
     p.add_argument("--no-ref", action="store_true")
+    p.add_argument("--precision", default="", choices=["", "f32", "f64"], help="solve mode: one solve per axis")
+    p.add_argument("--start", default="zero", choices=["zero", "linear", "learned"])
     p.add_argument("--max-steps", type=int, default=20_000_000)
     p.add_argument("--cells", type=int, default=64)
     p.add_argument("--seed", type=int, default=1503)
@@ -190,14 +192,35 @@ def mode_copy(args):
             "GB_s": round(8 * n / dt / 1e9, 1)}
 
 
-def _solve(m, prec, axis, sides, tol, args, T0=None, flux=False):
+def _solve(m, prec, axis, sides, tol, args, T0=None, flux=False, start="zero", net=None):
     import torch
 
-    g = _medium(m, prec, args)
+    from paper_1503_08718_amd import warmstart
+
+    mm = m
+    if start == "learned":
+        # the network works on media whose gradient runs along x
+        mm = m if axis == 0 else m.permuted({1: (1, 0, 2), 2: (2, 1, 0)}[axis])
+        axis = 0
+    g = _medium(mm, prec, args)
     g.set_bc(axis, 1.0, 0.0, (sides,) * 3)
-    g.init(T0, flux=flux)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
+    if start == "learned":
+        T, bad = warmstart.predict_start(net, mm, g)
+        if bad:
+            g.init()
+        else:
+            g.init(T.to(g.dtype), flux=True)
+    elif start == "linear":
+        shape = g.shape
+        n = shape[2 - axis]
+        lin = (1.0 - (torch.arange(n, dtype=torch.float64) + 0.5) / n).to(g.dtype)
+        view = [1, 1, 1]
+        view[2 - axis] = n
+        g.init(lin.view(*view).expand(*shape).contiguous().to(g.device), flux=True)
+    else:
+        g.init(T0, flux=flux)
+    torch.cuda.synchronize()
     r = g.solve(tol, "keff", args.max_steps, check_every=1000)
     torch.cuda.synchronize()
     r["seconds"] = round(time.perf_counter() - t0, 3)
@@ -205,23 +228,34 @@ def _solve(m, prec, axis, sides, tol, args, T0=None, flux=False):
 
 
 def mode_solve(args):
+    """Steady solves of one braided cell.  Default: FP32 from a zero start,
+    then an FP64 reference started from the FP32 field; with --precision the
+    single requested solve (from --start) is run instead."""
     import workloads
 
     m = workloads.braid(args.n, args.n, args.n, args.gamma, args.vf)
     out = {"mode": "solve", "workload": f"braided cell {args.n}^3, gamma {args.gamma}, yarn fraction {args.vf}, "
                                         f"{args.sides} sides", "tol": args.tol, "solves": []}
-    keys32 = ("keff", "keff_hot", "keff_cold", "keff_vol", "keff_col", "keff_leak", "steps", "seconds", "status")
+    keys = ("keff", "keff_hot", "keff_cold", "keff_vol", "keff_col", "keff_leak", "steps", "seconds", "status")
+    net = None
+    if args.start == "learned":
+        from paper_1503_08718_amd import warmstart
+
+        net = warmstart.Net.from_file(args.model, batch=1)
     for axis in [int(a) for a in args.axes.split(",")]:
-        g32, r32 = _solve(m, "f32", axis, args.sides, args.tol, args)
-        rec = {"axis": "xyz"[axis], "f32": {k: r32[k] for k in keys32}}
-        if not args.no_ref:
-            # FP64 reference, started from the FP32 field (with its flux part)
-            T = g32.temperature().double()
-            g64, r64 = _solve(m, "f64", axis, args.sides, args.ref_tol, args, T0=T, flux=True)
-            rec["f64_ref"] = {k: r64[k] for k in ("keff", "keff_hot", "keff_cold", "keff_vol", "steps", "seconds",
-                                                  "status")}
-            rec["f32_rel_err"] = abs(r32["keff"] - r64["keff"]) / abs(r64["keff"])
-            rec["f32_rel_err_vol"] = abs(r32["keff_vol"] - r64["keff_vol"]) / abs(r64["keff_vol"])
+        if args.precision:
+            g, r = _solve(m, args.precision, axis, args.sides, args.tol, args, start=args.start, net=net)
+            rec = {"axis": "xyz"[axis], "precision": args.precision, "start": args.start,
+                   "result": {k: r[k] for k in keys}, "MLUPS": round(m.phase.size * r["steps"] / r["seconds"] / 1e6, 1)}
+        else:
+            g32, r32 = _solve(m, "f32", axis, args.sides, args.tol, args)
+            rec = {"axis": "xyz"[axis], "f32": {k: r32[k] for k in keys}}
+            if not args.no_ref:
+                T = g32.temperature().double()
+                g64, r64 = _solve(m, "f64", axis, args.sides, args.ref_tol, args, T0=T, flux=True)
+                rec["f64_ref"] = {k: r64[k] for k in keys}
+                rec["f32_rel_err"] = abs(r32["keff"] - r64["keff"]) / abs(r64["keff"])
+                rec["f32_rel_err_vol"] = abs(r32["keff_vol"] - r64["keff_vol"]) / abs(r64["keff_vol"])
         out["solves"].append(rec)
         print(json.dumps(rec), flush=True)
     return out
