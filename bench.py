@@ -18,6 +18,8 @@ Other modes (each prints one JSON line):
                     batched, to k_eff at 1e-4: unit cells per hour
   --mode warmstart  held-out cells solved from a zero start and from the
                     learned warm start: steps and cells per hour
+  --mode paper      the paper's unit cell (Eqs. 32-37) over braiding angle
+                    and fibre fraction: k_T, k_L, trends, periodic vs adiabatic
 """
 
 from __future__ import annotations
@@ -35,16 +37,23 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 TUNE_CACHE = os.path.join(ROOT, "paper_1503_08718_amd", "tuned_launch.txt")
 WORKLOADS = {
-    # name: (n, precision, algorithmic bytes per lattice update of the step kernel)
-    "braid256_f32": (256, "f32", 57.0),
-    "braid128_f32": (128, "f32", 57.0),
-    "braid256_f64": (256, "f64", 113.0),
-    "braid128_f64": (128, "f64", 113.0),
+    # name: (n, precision)
+    "braid256_f32": (256, "f32"),
+    "braid128_f32": (128, "f32"),
+    "braid256_f64": (256, "f64"),
+    "braid128_f64": (128, "f64"),
 }
+STORAGE_VALUES = {"populations": 7, "moments": 4}
+
+
+def bytes_per_update(prec: str, storage: str) -> float:
+    """Algorithmic HBM bytes of one lattice update: the state read and
+    written once (7 populations or 4 moments) plus the phase byte."""
+    return 2.0 * STORAGE_VALUES[storage] * (8 if prec == "f64" else 4) + 1.0
 # HBM bytes per k_step launch on braid256_f32 from rocprofv3 --pmc FETCH_SIZE /
 # WRITE_SIZE (KiB per dispatch), each scaled by the counter's reading for a
 # plain copy of known size; None once the kernel changes.
-MEASURED_TRAFFIC = {("braid256_f32", (4, 64, 2, 3)): 956408366}
+MEASURED_TRAFFIC = {}
 
 
 def parse():
@@ -52,10 +61,12 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=4000)
     p.add_argument("--warmup", type=int, default=400)
-    p.add_argument("--mode", default="throughput", choices=["throughput", "copy", "solve", "sweep", "warmstart"])
+    p.add_argument("--mode", default="throughput",
+                   choices=["throughput", "copy", "solve", "sweep", "warmstart", "paper"])
     p.add_argument("--workload", default="braid256_f32", choices=sorted(WORKLOADS))
     p.add_argument("--check-every", type=int, default=200)
-    p.add_argument("--launch", default="", help="vec,bx,by[,nt] (default: autotune cache, else built-in)")
+    p.add_argument("--storage", default="moments", choices=sorted(STORAGE_VALUES))
+    p.add_argument("--launch", default="", help="vec,bx,by[,nt[,map]] (default: autotune cache, else built-in)")
     p.add_argument("--tune-cache", default=TUNE_CACHE)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-steps", type=int, default=0, help="oracle steps on the full cell (0 = auto)")
@@ -81,6 +92,7 @@ def _medium(m, prec, args):
     from paper_1503_08718_amd.solver import Medium
 
     g = Medium(m.phase, m.k, precision=prec, device="cuda:0")
+    g.set_storage(args.storage)
     if args.launch:
         g.set_launch(*[int(v) for v in args.launch.split(",")])
     elif os.path.exists(args.tune_cache):
@@ -112,7 +124,8 @@ def mode_throughput(args):
 
     import workloads
 
-    n, prec, bpl = WORKLOADS[args.workload]
+    n, prec = WORKLOADS[args.workload]
+    bpl = bytes_per_update(prec, args.storage)
     m = workloads.braid(n, n, n, 30.0, 0.5)
     g = _medium(m, prec, args)
     g.set_bc(0, 1.0, 0.0, ("periodic", "periodic", "periodic"))
@@ -132,8 +145,8 @@ def mode_throughput(args):
     ms = g.time_steps(kt_steps)
     kern_us = ms * 1e3 / kt_steps
     achieved = bpl * nodes / (kern_us * 1e-6) / 1e9
-    launch = dict(zip(("vec", "bx", "by", "nt"), g.info()["launch"]))
-    traffic = MEASURED_TRAFFIC.get((args.workload, tuple(launch.values())))
+    launch = dict(zip(("vec", "bx", "by", "nt", "map"), g.info()["launch"]))
+    traffic = MEASURED_TRAFFIC.get((args.workload, args.storage, tuple(launch.values())))
     line = {
         "metric": "MLUPS (million lattice updates per second) of the fused collide+stream step, with % of HBM peak",
         "value": round(mlups, 1),
@@ -151,6 +164,7 @@ def mode_throughput(args):
             "workload": f"synthetic four-directional braided cell {n}^3, braiding angle 30 deg, yarn fraction 0.5, "
                         f"k_axial 10 / k_trans 1 / matrix 0.2, x gradient, periodic sides, {prec.upper()}",
             "nodes": nodes,
+            "state_storage": args.storage,
             "check_every": K,
             "launch": launch,
         },
@@ -258,6 +272,18 @@ def mode_solve(args):
                 rec["f32_rel_err_vol"] = abs(r32["keff_vol"] - r64["keff_vol"]) / abs(r64["keff_vol"])
         out["solves"].append(rec)
         print(json.dumps(rec), flush=True)
+    axes_done = [int(a) for a in args.axes.split(",")]
+    if sorted(axes_done) == [0, 1, 2]:
+        # full effective tensor: column a is the mean flux of the a-gradient solve
+        import numpy as np
+
+        K = np.zeros((3, 3))
+        for a, rec in zip(axes_done, out["solves"]):
+            r = rec["result"] if "result" in rec else rec["f32"]
+            K[:, a] = r["keff_col"]
+        out["tensor"] = K.tolist()
+        out["tensor_asymmetry"] = float(np.abs(K - K.T).max() / np.abs(K).max())
+        out["tensor_eigenvalues"] = np.linalg.eigvalsh(0.5 * (K + K.T)).tolist()
     return out
 
 
@@ -302,6 +328,84 @@ def mode_sweep(args):
             "keff": {"xyz"[a]: [round(r["keff"], 6) for r in v[0]] for a, v in results.items()}}
 
 
+PAPER_TABLE3 = {  # interior braiding angle, fibre fraction -> (k_T, k_L), the paper's predictions (Table III)
+    (25, 0.5): (0.639, 3.085), (25, 0.58): (0.727, 3.444), (40, 0.5): (1.015, 2.258), (40, 0.58): (1.160, 2.583)}
+
+
+def paper_cells(angles, fractions, nxy=56):
+    """The paper's unit cell dimensions (Eqs. 32-35) and yarn properties
+    (Eqs. 36-37, epoxy 0.178, T300 7.81 / 0.675) on the synthetic braid."""
+    import workloads
+
+    cells = []
+    for phi in fractions:
+        lam_l, lam_t = workloads.yarn_conductivities(phi)
+        for g in angles:
+            geo = workloads.unit_cell_geometry(phi, g)
+            nz = int(round(nxy * geo["h"] / geo["a"]))
+            nz += nz % 2
+            cells.append(dict(gamma=g, phi_f=phi, nx=nxy, ny=nxy, nz=nz, lam_l=lam_l, lam_t=lam_t,
+                              a_mm=geo["a"], h_mm=geo["h"]))
+    return cells
+
+
+def mode_paper(args):
+    """Fig. 9-style sweep: k_T (x gradient) and k_L (z gradient) of braided
+    cells over interior braiding angle and fibre fraction, periodic sides,
+    plus adiabatic sides at 25 deg (Sec. 5.2); all cells of one axis and side
+    condition in one batched solve."""
+    import torch
+
+    import workloads
+    from paper_1503_08718_amd.solver import batch_solve
+
+    angles = [20, 25, 30, 35, 40, 45]
+    fractions = [0.4, 0.5, 0.58]
+    specs = paper_cells(angles, fractions)
+    media = [workloads.braid(c["nx"], c["ny"], c["nz"], c["gamma"], workloads.PHI_Y_EXACT, c["lam_l"], c["lam_t"],
+                             0.178) for c in specs]
+    out = {"mode": "paper", "tol": args.tol, "cells": []}
+    res = {}
+    for sides in ("periodic", "adiabatic"):
+        idx = range(len(specs)) if sides == "periodic" else [i for i, c in enumerate(specs) if c["gamma"] == 25]
+        for axis in (0, 2):
+            cells = []
+            for i in idx:
+                g = _medium(media[i], "f32", args)
+                g.set_bc(axis, 1.0, 0.0, (sides,) * 3)
+                g.init()
+                cells.append(g)
+            t0 = time.perf_counter()
+            r, st = batch_solve(cells, tol=args.tol, kind="keff", max_steps=args.max_steps, check_every=1000)
+            torch.cuda.synchronize()
+            print(json.dumps({"sides": sides, "axis": "xyz"[axis], "status": st,
+                              "seconds": round(time.perf_counter() - t0, 2)}), flush=True)
+            for i, rr in zip(idx, r):
+                res[(i, sides, axis)] = rr
+    for i, c in enumerate(specs):
+        rec = dict(c)
+        rec["k_T"] = res[(i, "periodic", 0)]["keff"]
+        rec["k_L"] = res[(i, "periodic", 2)]["keff"]
+        if (i, "adiabatic", 0) in res:
+            rec["k_T_adiabatic"] = res[(i, "adiabatic", 0)]["keff"]
+            rec["k_L_adiabatic"] = res[(i, "adiabatic", 2)]["keff"]
+        key = (c["gamma"], c["phi_f"])
+        if key in PAPER_TABLE3:
+            rec["paper_k_T"], rec["paper_k_L"] = PAPER_TABLE3[key]
+        out["cells"].append(rec)
+    kt = {(c["gamma"], c["phi_f"]): c["k_T"] for c in out["cells"]}
+    kl = {(c["gamma"], c["phi_f"]): c["k_L"] for c in out["cells"]}
+    out["trend_kT_rises_with_angle"] = all(kt[(a, f)] < kt[(b, f)] for f in fractions
+                                           for a, b in zip(angles, angles[1:]))
+    out["trend_kL_falls_with_angle"] = all(kl[(a, f)] > kl[(b, f)] for f in fractions
+                                           for a, b in zip(angles, angles[1:]))
+    out["trend_both_rise_with_fraction"] = all(kt[(a, f)] < kt[(a, g)] and kl[(a, f)] < kl[(a, g)]
+                                               for a in angles for f, g in zip(fractions, fractions[1:]))
+    out["periodic_above_adiabatic"] = all(c["k_T"] >= c["k_T_adiabatic"] and c["k_L"] >= c["k_L_adiabatic"]
+                                          for c in out["cells"] if "k_T_adiabatic" in c)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -321,6 +425,8 @@ def main():
         line = mode_solve(args)
     elif args.mode == "sweep":
         line = mode_sweep(args)
+    elif args.mode == "paper":
+        line = mode_paper(args)
     else:
         from paper_1503_08718_amd import warmstart
 

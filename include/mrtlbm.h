@@ -89,9 +89,12 @@ typedef struct {
  * consecutive x nodes; a block is bx x by threads over (x-vectors, rows).
  * vec in {1, 2, 4} (nx % vec == 0), bx in {8, 16, 32, 64}, bx*by in [64, 256]
  * and a multiple of 64, vec*bx >= 16.  nt: cache policy of the state
- * streams, bit 0 = non-temporal loads, bit 1 = non-temporal stores.
- * The batched solver uses vec and bx*by (threads per row tile) of cells[0]. */
-typedef struct { int vec, bx, by, nt; } mrtlbm_launch;
+ * streams, bit 0 = non-temporal loads, bit 1 = non-temporal stores.  map = 1:
+ * XCD-aware block order (each of the 8 XCDs sweeps one slab of rows through
+ * all planes, so rows and planes pulled from neighbours are still in that
+ * XCD's L2; used when the number of row blocks is a multiple of 8).
+ * The batched solver uses vec, bx*by (threads per row tile) and nt of cells[0]. */
+typedef struct { int vec, bx, by, nt, map; } mrtlbm_launch;
 
 /* Bytes of caller-owned device workspace a medium of these sizes needs
  * (two state buffers of 7 reals per node, reduction partials and tables),
@@ -161,11 +164,26 @@ mrtlbm_status mrtlbm_temperature(mrtlbm_medium *m, void *t_dev);
  * q_dev (real [3][nz][ny][nx]); async. */
 mrtlbm_status mrtlbm_flux(mrtlbm_medium *m, void *q_dev);
 
-/* Checkpoint / resume: copy the library's state (real [7][nz][ny][nx]; it is
- * the post-collision distribution minus w_i T_lin(x), T_lin the linear
- * profile between the two walls) out of or into the medium, device to
- * device, on the medium's stream.  A resumed medium continues bit for bit.
- * state_set also sets the step counter. */
+/* How the state is stored (Sec. 2.2: with tau_4 = tau_5 = tau_6 = 1 the
+ * post-collision state of a node is fixed by four moments, T and
+ * jhat = (I - tau^-1) j):
+ *   0 (default): the seven post-collision populations minus w_i T_lin(x),
+ *      real [7][nz][ny][nx] (T_lin: the linear profile between the walls);
+ *   1: the moments (T - T_lin(x), jhat_x/2, jhat_y/2, jhat_z/2),
+ *      real [4][nz][ny][nx]: 4 instead of 7 values per node and per step
+ *      read and written.  The populations are recomputed from them with the
+ *      operations that produce them in storage 0, so both storages give
+ *      bit-identical temperature and flux fields.
+ * Invalidates the state. */
+mrtlbm_status mrtlbm_set_storage(mrtlbm_medium *m, int storage);
+
+/* Values per node of the state: 7 (storage 0) or 4 (storage 1). */
+int mrtlbm_state_values(const mrtlbm_medium *m);
+
+/* Checkpoint / resume: copy the library's state (real [v][nz][ny][nx],
+ * v = mrtlbm_state_values, layout as for mrtlbm_set_storage) out of or into
+ * the medium, device to device, on the medium's stream.  A resumed medium
+ * continues bit for bit.  state_set also sets the step counter. */
 mrtlbm_status mrtlbm_state_get(mrtlbm_medium *m, void *f_dev);
 mrtlbm_status mrtlbm_state_set(mrtlbm_medium *m, const void *f_dev, long long steps);
 

@@ -47,7 +47,8 @@ class Result(ctypes.Structure):
 
 
 class Launch(ctypes.Structure):
-    _fields_ = [("vec", ctypes.c_int), ("bx", ctypes.c_int), ("by", ctypes.c_int), ("nt", ctypes.c_int)]
+    _fields_ = [("vec", ctypes.c_int), ("bx", ctypes.c_int), ("by", ctypes.c_int), ("nt", ctypes.c_int),
+                ("map", ctypes.c_int)]
 
 
 _lib = None
@@ -110,6 +111,8 @@ def load():
         "mrtlbm_flux": (I, [P, P]),
         "mrtlbm_state_get": (I, [P, P]),
         "mrtlbm_state_set": (I, [P, P, LL]),
+        "mrtlbm_set_storage": (I, [P, I]),
+        "mrtlbm_state_values": (I, [P]),
         "mrtlbm_info": (I, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong), LP]),
         "mrtlbm_set_launch": (I, [P, LP]),
         "mrtlbm_autotune": (I, [P, ctypes.c_char_p, LP]),

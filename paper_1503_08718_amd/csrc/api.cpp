@@ -174,6 +174,7 @@ bool mrt::launch_ok(const mrtlbm_medium *m, const Launch &L) {
     if (L.by < 1 || t < 64 || t > 256 || (t % 64)) return false;
     if (L.vec * L.bx < 16) return false;
     if (L.nt < 0 || L.nt > 3) return false;
+    if (L.map < 0 || L.map > 1) return false;
     return true;
 }
 
@@ -188,6 +189,7 @@ Launch mrt::default_launch(const mrtlbm_medium *m) {
     L.bx = bx;
     L.by = 256 / bx;
     L.nt = 0;
+    L.map = 0;
     return L;
 }
 
@@ -215,6 +217,7 @@ Cell<real> mrt::make_cell(const mrtlbm_medium *m, int cur) {
         c.h[a] = grad ? (real)(0.25 * dT / (2.0 * ext[a])) : real(0);
     }
     c.gaxis = m->gaxis;
+    c.storage = m->storage;
     return c;
 }
 template Cell<float> mrt::make_cell<float>(const mrtlbm_medium *, int);
@@ -383,13 +386,14 @@ extern "C" mrtlbm_status mrtlbm_info(const mrtlbm_medium *m, double *scale, long
     if (steps) *steps = m->steps;
     if (launch) {
         launch->vec = m->launch.vec; launch->bx = m->launch.bx; launch->by = m->launch.by; launch->nt = m->launch.nt;
+        launch->map = m->launch.map;
     }
     return MRTLBM_OK;
 }
 
 extern "C" mrtlbm_status mrtlbm_set_launch(mrtlbm_medium *m, const mrtlbm_launch *launch) {
     if (!m) return fail(MRTLBM_E_ARG, "medium is NULL");
-    Launch L = launch ? Launch{launch->vec, launch->bx, launch->by, launch->nt} : default_launch(m);
+    Launch L = launch ? Launch{launch->vec, launch->bx, launch->by, launch->nt, launch->map} : default_launch(m);
     if (!launch_ok(m, L))
         return fail(MRTLBM_E_ARG, "launch shape vec=%d bx=%d by=%d nt=%d not admissible", L.vec, L.bx, L.by, L.nt);
     drop_graphs(m);
@@ -647,10 +651,21 @@ extern "C" mrtlbm_status mrtlbm_solve(mrtlbm_medium *m, double tol, mrtlbm_tol_k
 // checkpoint / resume
 // ---------------------------------------------------------------------------
 
+extern "C" int mrtlbm_state_values(const mrtlbm_medium *m) { return !m ? 0 : (m->storage ? 4 : Q); }
+
+extern "C" mrtlbm_status mrtlbm_set_storage(mrtlbm_medium *m, int storage) {
+    if (!m) return fail(MRTLBM_E_ARG, "medium is NULL");
+    if (storage != 0 && storage != 1) return fail(MRTLBM_E_ARG, "storage must be 0 or 1");
+    m->storage = storage;
+    m->initialised = false;
+    drop_graphs(m);
+    return MRTLBM_OK;
+}
+
 extern "C" mrtlbm_status mrtlbm_state_get(mrtlbm_medium *m, void *f_dev) {
     if (!m || !f_dev) return fail(MRTLBM_E_ARG, "NULL argument");
     if (!m->initialised) return fail(MRTLBM_E_ARG, "state not initialised");
-    const size_t bytes = (size_t)Q * m->N * (m->prec == MRTLBM_F64 ? 8 : 4);
+    const size_t bytes = (size_t)mrtlbm_state_values(m) * m->N * (m->prec == MRTLBM_F64 ? 8 : 4);
     HIPCHK(hipMemcpyAsync(f_dev, m->cur ? m->bufB : m->bufA, bytes, hipMemcpyDeviceToDevice, m->stream));
     return MRTLBM_OK;
 }
@@ -658,7 +673,7 @@ extern "C" mrtlbm_status mrtlbm_state_get(mrtlbm_medium *m, void *f_dev) {
 extern "C" mrtlbm_status mrtlbm_state_set(mrtlbm_medium *m, const void *f_dev, long long steps) {
     if (!m || !f_dev) return fail(MRTLBM_E_ARG, "NULL argument");
     if (steps < 0) return fail(MRTLBM_E_ARG, "steps < 0");
-    const size_t bytes = (size_t)Q * m->N * (m->prec == MRTLBM_F64 ? 8 : 4);
+    const size_t bytes = (size_t)mrtlbm_state_values(m) * m->N * (m->prec == MRTLBM_F64 ? 8 : 4);
     HIPCHK(hipMemcpyAsync(m->bufA, f_dev, bytes, hipMemcpyDeviceToDevice, m->stream));
     m->cur = 0;
     m->steps = steps;
@@ -695,7 +710,8 @@ static std::string tune_key(const mrtlbm_medium *m) {
         if (c != std::string::npos) arch = arch.substr(0, c);
     }
     std::ostringstream k;
-    k << arch << ' ' << m->nx << ' ' << m->ny << ' ' << m->nz << ' ' << (m->prec == MRTLBM_F64 ? "f64" : "f32");
+    k << arch << ' ' << m->nx << ' ' << m->ny << ' ' << m->nz << ' ' << (m->prec == MRTLBM_F64 ? "f64" : "f32")
+      << (m->storage ? "m" : "d");
     return k.str();
 }
 
@@ -703,7 +719,8 @@ extern "C" mrtlbm_status mrtlbm_autotune(mrtlbm_medium *m, const char *cache_pat
     if (!m) return fail(MRTLBM_E_ARG, "medium is NULL");
     mrtlbm_status st = mrtlbm_init(m, nullptr, 0);
     if (st != MRTLBM_OK) return st;
-    const double bytes_per_step = (double)m->N * (m->prec == MRTLBM_F64 ? 113.0 : 57.0);
+    const double rs = (m->prec == MRTLBM_F64) ? 8.0 : 4.0;
+    const double bytes_per_step = (double)m->N * (2.0 * mrtlbm_state_values(m) * rs + 1.0);
     long long n = (long long)std::ceil(2e10 / bytes_per_step);
     n = std::max(4LL, std::min(n, 2000LL));
     n += (n & 1);
@@ -713,8 +730,10 @@ extern "C" mrtlbm_status mrtlbm_autotune(mrtlbm_medium *m, const char *cache_pat
     for (int vec : {4, 2, 1})
         for (int bx : {8, 16, 32, 64})
             for (int t : {64, 128, 256})
-                for (int nt : {0, 1, 2, 3}) {
-                Launch L{vec, bx, t / bx, nt};
+                for (int nt : {0, 1, 2, 3})
+                    for (int map : {0, 1}) {
+                Launch L{vec, bx, t / bx, nt, map};
+                if (map && ((m->ny + L.by - 1) / L.by) % 8) continue;  // remap needs 8 | row blocks
                 if (t % bx || !launch_ok(m, L)) continue;
                 if (L.bx > 2 * std::max(8, m->nx / vec)) continue;  // mostly idle lanes
                 m->launch = L;
@@ -734,7 +753,9 @@ extern "C" mrtlbm_status mrtlbm_autotune(mrtlbm_medium *m, const char *cache_pat
     m->launch = bestL;
     drop_graphs(m);
     m->initialised = false;
-    if (best) { best->vec = bestL.vec; best->bx = bestL.bx; best->by = bestL.by; best->nt = bestL.nt; }
+    if (best) {
+        best->vec = bestL.vec; best->bx = bestL.bx; best->by = bestL.by; best->nt = bestL.nt; best->map = bestL.map;
+    }
     if (cache_path) {
         const std::string key = tune_key(m);
         std::vector<std::string> lines;
@@ -745,7 +766,8 @@ extern "C" mrtlbm_status mrtlbm_autotune(mrtlbm_medium *m, const char *cache_pat
                 if (line.compare(0, key.size() + 1, key + " ") != 0 && !line.empty()) lines.push_back(line);
         }
         std::ostringstream l;
-        l << key << ' ' << bestL.vec << ' ' << bestL.bx << ' ' << bestL.by << ' ' << bestL.nt << ' ' << (bestms / n);
+        l << key << ' ' << bestL.vec << ' ' << bestL.bx << ' ' << bestL.by << ' ' << bestL.nt << ' ' << bestL.map << ' '
+          << (bestms / n);
         lines.push_back(l.str());
         std::ofstream o(cache_path, std::ios::trunc);
         for (auto &s : lines) o << s << '\n';
@@ -763,7 +785,7 @@ extern "C" mrtlbm_status mrtlbm_load_tuned(mrtlbm_medium *m, const char *cache_p
         if (line.compare(0, key.size() + 1, key + " ") != 0) continue;
         std::istringstream r(line.substr(key.size() + 1));
         Launch L{};
-        if (r >> L.vec >> L.bx >> L.by >> L.nt && launch_ok(m, L)) {
+        if (r >> L.vec >> L.bx >> L.by >> L.nt >> L.map && launch_ok(m, L)) {
             drop_graphs(m);
             m->launch = L;
             return MRTLBM_OK;

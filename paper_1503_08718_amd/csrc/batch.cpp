@@ -44,7 +44,7 @@ bool batch_layout(mrtlbm_medium *const *cells, int n, BatchLayout *L) {
 struct BatchRun {
     mrtlbm_medium *const *cells;
     int n;
-    int vec, threads, max_nphase, nt;
+    int vec, threads, max_nphase, nt, storage;
     char *ws;
     BatchLayout lay;
     hipStream_t stream, cap;
@@ -111,7 +111,7 @@ mrtlbm_status build_graph(BatchRun &B, int K) {
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     for (int i = 0; i < K && e == hipSuccess; i++)
         e = launch_batch<real>(cells, tiles, B.ntiles, B.vec, B.threads, B.max_nphase, i & 1, i == K - 1, B.nt,
-                               partials, B.cap);
+                               B.storage, partials, B.cap);
     if (e == hipSuccess) e = launch_batch_reduce(partials, start, (int)B.active.size(), finals, B.cap);
     if (e == hipSuccess)
         e = hipMemcpyAsync(B.pinned, finals, B.active.size() * NRED * sizeof(double), hipMemcpyDeviceToHost, B.cap);
@@ -200,6 +200,7 @@ extern "C" mrtlbm_status mrtlbm_batch_solve(mrtlbm_medium *const *cells, int n, 
         const mrtlbm_medium *m = cells[i];
         if (!m->initialised) return fail(MRTLBM_E_ARG, "cell %d is not initialised", i);
         if (m->prec != m0->prec) return fail(MRTLBM_E_ARG, "cells mix precisions");
+        if (m->storage != m0->storage) return fail(MRTLBM_E_ARG, "cells mix state storages");
         if (m->stream != m0->stream || m->device != m0->device) return fail(MRTLBM_E_ARG, "cells mix streams/devices");
         while (m->nx % vec) vec >>= 1;
         max_nphase = std::max(max_nphase, m->nphase);
@@ -218,6 +219,7 @@ extern "C" mrtlbm_status mrtlbm_batch_solve(mrtlbm_medium *const *cells, int n, 
     B.threads = threads;
     B.max_nphase = max_nphase;
     B.nt = m0->launch.nt;
+    B.storage = m0->storage;
     B.ws = (char *)workspace_dev;
     B.lay = lay;
     B.stream = m0->stream;

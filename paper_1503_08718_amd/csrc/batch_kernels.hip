@@ -27,7 +27,7 @@ __device__ __forceinline__ XLink packed_links(int xv, int nxv) {
 }
 
 // tile = (cell, z-plane, first row y0, number of rows)
-template <typename real, int VEC, int MODE, int NT>
+template <typename real, int VEC, int MODE, int NT, int ST>
 __global__ void __launch_bounds__(256) k_batch(const Cell<real> *__restrict__ cells, const int4 *__restrict__ tiles,
                                                int parity, double *partials) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(256) k_batch(const Cell<real> *__restrict__ ce
     const int z = tile.y;
     Acc acc;
     acc.zero();
-    node_update<real, VEC, MODE, NT>(c, tab, xv, y, z, active, packed_links(xv, c.nxv), acc, nullptr, real(0));
+    node_update<real, VEC, MODE, NT, ST>(c, tab, xv, y, z, active, packed_links(xv, c.nxv), acc, nullptr, real(0));
     if constexpr (MODE == 1) block_reduce_store(acc, partials + (long long)blockIdx.x * NRED);
 }
 
@@ -79,25 +79,32 @@ __global__ void __launch_bounds__(256) k_batch_reduce(const double *__restrict__
     if (t < NRED) finals[(long long)cell * NRED + t] = red[0][t];
 }
 
+template <typename real, int VEC, int ST>
+static void launch_batch_st(const Cell<real> *cells, const int4 *tiles, int ntiles, int threads, size_t sh, int parity,
+                            bool check, int nt, double *partials, hipStream_t s) {
+    const dim3 g(ntiles), b(threads);
+    if (check) hipLaunchKernelGGL((k_batch<real, VEC, 1, 0, ST>), g, b, sh, s, cells, tiles, parity, partials);
+    else if (nt == 3) hipLaunchKernelGGL((k_batch<real, VEC, 0, 3, ST>), g, b, sh, s, cells, tiles, parity, partials);
+    else if (nt == 2) hipLaunchKernelGGL((k_batch<real, VEC, 0, 2, ST>), g, b, sh, s, cells, tiles, parity, partials);
+    else if (nt == 1) hipLaunchKernelGGL((k_batch<real, VEC, 0, 1, ST>), g, b, sh, s, cells, tiles, parity, partials);
+    else hipLaunchKernelGGL((k_batch<real, VEC, 0, 0, ST>), g, b, sh, s, cells, tiles, parity, partials);
+}
+
 template <typename real, int VEC>
 static void launch_batch_vec(const Cell<real> *cells, const int4 *tiles, int ntiles, int threads, size_t sh, int parity,
-                             bool check, int nt, double *partials, hipStream_t s) {
-    const dim3 g(ntiles), b(threads);
-    if (check) hipLaunchKernelGGL((k_batch<real, VEC, 1, 0>), g, b, sh, s, cells, tiles, parity, partials);
-    else if (nt == 3) hipLaunchKernelGGL((k_batch<real, VEC, 0, 3>), g, b, sh, s, cells, tiles, parity, partials);
-    else if (nt == 2) hipLaunchKernelGGL((k_batch<real, VEC, 0, 2>), g, b, sh, s, cells, tiles, parity, partials);
-    else if (nt == 1) hipLaunchKernelGGL((k_batch<real, VEC, 0, 1>), g, b, sh, s, cells, tiles, parity, partials);
-    else hipLaunchKernelGGL((k_batch<real, VEC, 0, 0>), g, b, sh, s, cells, tiles, parity, partials);
+                             bool check, int nt, int storage, double *partials, hipStream_t s) {
+    if (storage) launch_batch_st<real, VEC, 1>(cells, tiles, ntiles, threads, sh, parity, check, nt, partials, s);
+    else launch_batch_st<real, VEC, 0>(cells, tiles, ntiles, threads, sh, parity, check, nt, partials, s);
 }
 
 template <typename real>
 hipError_t launch_batch(const Cell<real> *cells, const int4 *tiles, int ntiles, int vec, int threads, int max_nphase,
-                        int parity, bool check, int nt, double *partials, hipStream_t s) {
+                        int parity, bool check, int nt, int storage, double *partials, hipStream_t s) {
     const size_t sh = sizeof(real) * TABW * max_nphase;
     switch (vec) {
-        case 4: launch_batch_vec<real, 4>(cells, tiles, ntiles, threads, sh, parity, check, nt, partials, s); break;
-        case 2: launch_batch_vec<real, 2>(cells, tiles, ntiles, threads, sh, parity, check, nt, partials, s); break;
-        default: launch_batch_vec<real, 1>(cells, tiles, ntiles, threads, sh, parity, check, nt, partials, s); break;
+        case 4: launch_batch_vec<real, 4>(cells, tiles, ntiles, threads, sh, parity, check, nt, storage, partials, s); break;
+        case 2: launch_batch_vec<real, 2>(cells, tiles, ntiles, threads, sh, parity, check, nt, storage, partials, s); break;
+        default: launch_batch_vec<real, 1>(cells, tiles, ntiles, threads, sh, parity, check, nt, storage, partials, s); break;
     }
     return hipGetLastError();
 }
@@ -107,9 +114,9 @@ hipError_t launch_batch_reduce(const double *partials, const int *start, int nce
     return hipGetLastError();
 }
 
-template hipError_t launch_batch<float>(const Cell<float> *, const int4 *, int, int, int, int, int, bool, int,
+template hipError_t launch_batch<float>(const Cell<float> *, const int4 *, int, int, int, int, int, bool, int, int,
                                         double *, hipStream_t);
-template hipError_t launch_batch<double>(const Cell<double> *, const int4 *, int, int, int, int, int, bool, int,
+template hipError_t launch_batch<double>(const Cell<double> *, const int4 *, int, int, int, int, int, bool, int, int,
                                          double *, hipStream_t);
 
 }  // namespace mrt

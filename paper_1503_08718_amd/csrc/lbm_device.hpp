@@ -79,18 +79,30 @@ struct XLink {
     bool haveL, haveR;
 };
 
+// What one thread pulled for its VEC nodes: the rest population, the six
+// streamed populations before the gradient-axis shift (wall links already
+// reflected), the node's own populations summed (T(t), check modes only), the
+// phases, and the populations that left through an isothermal wall.
+template <typename real, int VEC>
+struct Pulled {
+    real f0[VEC], r[6][VEC];
+    real told[VEC];
+    int ph[VEC];
+    double out_hot, out_cold;  // sums of the outgoing wall populations of this thread's nodes
+    bool hot, cold;            // this thread holds nodes on the hot / cold face
+};
+
+// Distribution storage: state [7][N].
 // MODE 0: step; 1: step + observables; 2: observables only; 3: as 2 + flux field.
 // NT bit 0: non-temporal state loads; bit 1: non-temporal state stores.
-template <typename real, int VEC, int MODE, int NT = 0>
-__device__ __forceinline__ void node_update(const Cell<real> &c, const real *__restrict__ tab, int xv, int y, int z,
-                                            bool active, const XLink &xl, Acc &acc, real *__restrict__ qout,
-                                            real qscale) {
+template <typename real, int VEC, int MODE, int NT>
+__device__ __forceinline__ void pull_dist(const Cell<real> &c, int xv, int y, int z, const XLink &xl,
+                                          Pulled<real, VEC> &P) {
     const long long N = c.N;
     const int nx = c.nx, ny = c.ny, nz = c.nz;
     const int x0 = xv * VEC;
     const long long base = ((long long)z * ny + y) * nx + x0;
     const real *__restrict__ s = c.src;
-
     // neighbour rows/planes; on a non-periodic wall redirect to the opposite
     // population of the node itself (the reflected link)
     int ym = y - 1, yp = y + 1, pym = 3, pyp = 4;
@@ -101,30 +113,29 @@ __device__ __forceinline__ void node_update(const Cell<real> &c, const real *__r
     const bool zlo = (z == 0), zhi = (z == nz - 1);
     if (zlo) { if (c.per[2]) zm = nz - 1; else { zm = z; pzm = 6; } }
     if (zhi) { if (c.per[2]) zp = 0; else { zp = z; pzp = 5; } }
-
-    Vec<real, VEC> c0 = vload<real, VEC, (NT & 1) != 0>(s + base);
-    Vec<real, VEC> a1 = vload<real, VEC, (NT & 1) != 0>(s + N + base);
-    Vec<real, VEC> a2 = vload<real, VEC, (NT & 1) != 0>(s + 2 * N + base);
-    Vec<real, VEC> b3 = vload<real, VEC, (NT & 1) != 0>(s + pym * N + ((long long)z * ny + ym) * nx + x0);
-    Vec<real, VEC> b4 = vload<real, VEC, (NT & 1) != 0>(s + pyp * N + ((long long)z * ny + yp) * nx + x0);
-    Vec<real, VEC> b5 = vload<real, VEC, (NT & 1) != 0>(s + pzm * N + ((long long)zm * ny + y) * nx + x0);
-    Vec<real, VEC> b6 = vload<real, VEC, (NT & 1) != 0>(s + pzp * N + ((long long)zp * ny + y) * nx + x0);
-    int ph[VEC];
-    load_phase<VEC>(c.phase + base, ph);
-    Vec<real, VEC> o3, o4, o5, o6;
+    constexpr bool NL = (NT & 1) != 0;
+    Vec<real, VEC> c0 = vload<real, VEC, NL>(s + base);
+    Vec<real, VEC> a1 = vload<real, VEC, NL>(s + N + base);
+    Vec<real, VEC> a2 = vload<real, VEC, NL>(s + 2 * N + base);
+    Vec<real, VEC> b3 = vload<real, VEC, NL>(s + pym * N + ((long long)z * ny + ym) * nx + x0);
+    Vec<real, VEC> b4 = vload<real, VEC, NL>(s + pyp * N + ((long long)z * ny + yp) * nx + x0);
+    Vec<real, VEC> b5 = vload<real, VEC, NL>(s + pzm * N + ((long long)zm * ny + y) * nx + x0);
+    Vec<real, VEC> b6 = vload<real, VEC, NL>(s + pzp * N + ((long long)zp * ny + y) * nx + x0);
+    load_phase<VEC>(c.phase + base, P.ph);
     if constexpr (MODE != 0) {  // own post-collision populations: T(t) for the residual
-        o3 = vload<real, VEC>(s + 3 * N + base);
-        o4 = vload<real, VEC>(s + 4 * N + base);
-        o5 = vload<real, VEC>(s + 5 * N + base);
-        o6 = vload<real, VEC>(s + 6 * N + base);
+        Vec<real, VEC> o3 = vload<real, VEC>(s + 3 * N + base);
+        Vec<real, VEC> o4 = vload<real, VEC>(s + 4 * N + base);
+        Vec<real, VEC> o5 = vload<real, VEC>(s + 5 * N + base);
+        Vec<real, VEC> o6 = vload<real, VEC>(s + 6 * N + base);
+#pragma unroll
+        for (int v = 0; v < VEC; v++)
+            P.told[v] = c0.v[v] + a1.v[v] + a2.v[v] + o3.v[v] + o4.v[v] + o5.v[v] + o6.v[v];
     }
-
     // x exchange inside the wave: my last g1 feeds the next lane's first
     // node, my first g2 feeds the previous lane's last node
     const real gotL = __shfl(a1.v[VEC - 1], min(max(xl.srcL, 0), 63), 64);
     const real gotR = __shfl(a2.v[0], min(max(xl.srcR, 0), 63), 64);
     real left, right;
-    const real hx = c.h[0], hy = c.h[1], hz = c.h[2];
     real rawHotX = 0, rawColdX = 0;
     if (x0 == 0) {
         if (c.per[0]) left = xl.haveL ? gotL : s[N + base + nx - 1];
@@ -142,36 +153,165 @@ __device__ __forceinline__ void node_update(const Cell<real> &c, const real *__r
     const real sy4 = (yhi && !c.per[1]) ? c.sgn[1] : real(1);
     const real sz5 = (zlo && !c.per[2]) ? c.sgn[2] : real(1);
     const real sz6 = (zhi && !c.per[2]) ? c.sgn[2] : real(1);
-
-    Vec<real, VEC> out[Q];
 #pragma unroll
     for (int v = 0; v < VEC; v++) {
-        const real f0 = c0.v[v];
-        const real r1 = (v == 0 ? left : a1.v[v - 1]);
-        const real r2 = (v == VEC - 1 ? right : a2.v[v + 1]);
-        const real r3 = sy3 * b3.v[v], r4 = sy4 * b4.v[v];
-        const real r5 = sz5 * b5.v[v], r6 = sz6 * b6.v[v];
-        const real f1 = r1 + hx, f2 = r2 - hx;
-        const real f3 = r3 + hy, f4 = r4 - hy;
-        const real f5 = r5 + hz, f6 = r6 - hz;
+        P.f0[v] = c0.v[v];
+        P.r[0][v] = (v == 0 ? left : a1.v[v - 1]);
+        P.r[1][v] = (v == VEC - 1 ? right : a2.v[v + 1]);
+        P.r[2][v] = sy3 * b3.v[v];
+        P.r[3][v] = sy4 * b4.v[v];
+        P.r[4][v] = sz5 * b5.v[v];
+        P.r[5][v] = sz6 * b6.v[v];
+    }
+    if constexpr (MODE != 0) {
+        P.out_hot = P.out_cold = 0.0;
+        const int g = c.gaxis;
+        if (g == 0) {
+            P.hot = (x0 == 0);
+            P.cold = (x0 + VEC == nx);
+            P.out_hot = rawHotX;
+            P.out_cold = rawColdX;
+        } else {
+            const Vec<real, VEC> &bh = (g == 1) ? b3 : b5;
+            const Vec<real, VEC> &bc = (g == 1) ? b4 : b6;
+            P.hot = (g == 1) ? ylo : zlo;
+            P.cold = (g == 1) ? yhi : zhi;
+#pragma unroll
+            for (int v = 0; v < VEC; v++) {
+                P.out_hot += (double)bh.v[v];
+                P.out_cold += (double)bc.v[v];
+            }
+        }
+    }
+}
+
+// Moment storage: state [4][N] = (T - T_lin, jhat_x / 2, jhat_y / 2, jhat_z / 2).
+// With tau_4 = tau_5 = tau_6 = 1 the post-collision populations are
+// g_0 = T/4 and g_{2a+1, 2a+2} = T/8 +- jhat_a/2, recomputed here with the
+// very operations that produced them in distribution storage, so both
+// storages evolve bit for bit alike.
+template <typename real>
+__device__ __forceinline__ real gplus(real T, real z) { return T * real(0.125) + z; }
+template <typename real>
+__device__ __forceinline__ real gminus(real T, real z) { return T * real(0.125) - z; }
+
+template <typename real, int VEC, int MODE, int NT>
+__device__ __forceinline__ void pull_mom(const Cell<real> &c, int xv, int y, int z, const XLink &xl,
+                                         Pulled<real, VEC> &P) {
+    const long long N = c.N;
+    const int nx = c.nx, ny = c.ny, nz = c.nz;
+    const int x0 = xv * VEC;
+    const long long row = (long long)z * ny + y;
+    const long long base = row * nx + x0;
+    const real *__restrict__ sT = c.src;
+    const real *__restrict__ sX = c.src + N;
+    const real *__restrict__ sY = c.src + 2 * N;
+    const real *__restrict__ sZ = c.src + 3 * N;
+    const bool ylo = (y == 0), yhi = (y == ny - 1), zlo = (z == 0), zhi = (z == nz - 1);
+    // a wall link reads the node's own opposite population: own row, other sign of jhat
+    const int ym = ylo ? (c.per[1] ? ny - 1 : y) : y - 1;
+    const int yp = yhi ? (c.per[1] ? 0 : y) : y + 1;
+    const int zm = zlo ? (c.per[2] ? nz - 1 : z) : z - 1;
+    const int zp = zhi ? (c.per[2] ? 0 : z) : z + 1;
+    const bool wym = ylo && !c.per[1], wyp = yhi && !c.per[1], wzm = zlo && !c.per[2], wzp = zhi && !c.per[2];
+    constexpr bool NL = (NT & 1) != 0;
+    Vec<real, VEC> Tc = vload<real, VEC, NL>(sT + base);
+    Vec<real, VEC> Xc = vload<real, VEC, NL>(sX + base);
+    const long long rym = ((long long)z * ny + ym) * nx + x0, ryp = ((long long)z * ny + yp) * nx + x0;
+    const long long rzm = ((long long)zm * ny + y) * nx + x0, rzp = ((long long)zp * ny + y) * nx + x0;
+    Vec<real, VEC> Tym = vload<real, VEC, NL>(sT + rym), Yym = vload<real, VEC, NL>(sY + rym);
+    Vec<real, VEC> Typ = vload<real, VEC, NL>(sT + ryp), Yyp = vload<real, VEC, NL>(sY + ryp);
+    Vec<real, VEC> Tzm = vload<real, VEC, NL>(sT + rzm), Zzm = vload<real, VEC, NL>(sZ + rzm);
+    Vec<real, VEC> Tzp = vload<real, VEC, NL>(sT + rzp), Zzp = vload<real, VEC, NL>(sZ + rzp);
+    load_phase<VEC>(c.phase + base, P.ph);
+    // x: my last g1 feeds the next lane, my first g2 the previous lane
+    const real mine1 = gplus(Tc.v[VEC - 1], Xc.v[VEC - 1]);
+    const real mine2 = gminus(Tc.v[0], Xc.v[0]);
+    const real gotL = __shfl(mine1, min(max(xl.srcL, 0), 63), 64);
+    const real gotR = __shfl(mine2, min(max(xl.srcR, 0), 63), 64);
+    real left, right;
+    if (x0 == 0) {
+        if (c.per[0]) left = xl.haveL ? gotL : gplus(sT[base + nx - 1], sX[base + nx - 1]);
+        else left = c.sgn[0] * mine2;
+    } else {
+        left = xl.haveL ? gotL : gplus(sT[base - 1], sX[base - 1]);
+    }
+    if (x0 + VEC == nx) {
+        if (c.per[0]) right = xl.haveR ? gotR : gminus(sT[base - x0], sX[base - x0]);
+        else right = c.sgn[0] * mine1;
+    } else {
+        right = xl.haveR ? gotR : gminus(sT[base + VEC], sX[base + VEC]);
+    }
+    Vec<real, VEC> Yc, Zc;
+    if constexpr (MODE != 0) {
+        Yc = vload<real, VEC>(sY + base);
+        Zc = vload<real, VEC>(sZ + base);
+    }
+#pragma unroll
+    for (int v = 0; v < VEC; v++) {
+        P.f0[v] = Tc.v[v] * real(0.25);
+        P.r[0][v] = (v == 0) ? left : gplus(Tc.v[v - 1], Xc.v[v - 1]);
+        P.r[1][v] = (v == VEC - 1) ? right : gminus(Tc.v[v + 1], Xc.v[v + 1]);
+        P.r[2][v] = wym ? c.sgn[1] * gminus(Tym.v[v], Yym.v[v]) : gplus(Tym.v[v], Yym.v[v]);
+        P.r[3][v] = wyp ? c.sgn[1] * gplus(Typ.v[v], Yyp.v[v]) : gminus(Typ.v[v], Yyp.v[v]);
+        P.r[4][v] = wzm ? c.sgn[2] * gminus(Tzm.v[v], Zzm.v[v]) : gplus(Tzm.v[v], Zzm.v[v]);
+        P.r[5][v] = wzp ? c.sgn[2] * gplus(Tzp.v[v], Zzp.v[v]) : gminus(Tzp.v[v], Zzp.v[v]);
+        if constexpr (MODE != 0) {
+            const real t = Tc.v[v];
+            P.told[v] = t * real(0.25) + gplus(t, Xc.v[v]) + gminus(t, Xc.v[v]) + gplus(t, Yc.v[v]) +
+                        gminus(t, Yc.v[v]) + gplus(t, Zc.v[v]) + gminus(t, Zc.v[v]);
+        }
+    }
+    if constexpr (MODE != 0) {
+        P.out_hot = P.out_cold = 0.0;
+        const int g = c.gaxis;
+        if (g == 0) {
+            P.hot = (x0 == 0);
+            P.cold = (x0 + VEC == nx);
+            P.out_hot = (double)mine2;
+            P.out_cold = (double)mine1;
+        } else {
+            P.hot = (g == 1) ? ylo : zlo;
+            P.cold = (g == 1) ? yhi : zhi;
+#pragma unroll
+            for (int v = 0; v < VEC; v++) {
+                const real jh = (g == 1) ? Yc.v[v] : Zc.v[v];
+                P.out_hot += (double)gminus(Tc.v[v], jh);
+                P.out_cold += (double)gplus(Tc.v[v], jh);
+            }
+        }
+    }
+}
+
+// Collision (shared by both storages), FP64 observables, and the stores.
+// STORAGE 0: 7 populations; 1: 4 moments.
+template <typename real, int VEC, int MODE, int NT, int STORAGE>
+__device__ __forceinline__ void collide_store(const Cell<real> &c, const real *__restrict__ tab, int xv, int y, int z,
+                                              bool active, const Pulled<real, VEC> &P, Acc &acc,
+                                              real *__restrict__ qout, real qscale) {
+    const long long N = c.N;
+    const long long base = ((long long)z * c.ny + y) * c.nx + xv * VEC;
+    const real hx = c.h[0], hy = c.h[1], hz = c.h[2];
+    Vec<real, VEC> T_, X_, Y_, Z_;
+#pragma unroll
+    for (int v = 0; v < VEC; v++) {
+        const real f0 = P.f0[v];
+        const real f1 = P.r[0][v] + hx, f2 = P.r[1][v] - hx;
+        const real f3 = P.r[2][v] + hy, f4 = P.r[3][v] - hy;
+        const real f5 = P.r[4][v] + hz, f6 = P.r[5][v] - hz;
         const real T = f0 + f1 + f2 + f3 + f4 + f5 + f6;
         const real jx = f1 - f2, jy = f3 - f4, jz = f5 - f6;
-        const real *tb = tab + ph[v] * TABW;  // half of (I - tau^-1)
+        const real *tb = tab + P.ph[v] * TABW;  // half of (I - tau^-1)
         const real hjx = tb[0] * jx + tb[3] * jy + tb[4] * jz;
         const real hjy = tb[3] * jx + tb[1] * jy + tb[5] * jz;
         const real hjz = tb[4] * jx + tb[5] * jy + tb[2] * jz;
-        const real t8 = T * real(0.125);
-        out[0].v[v] = T * real(0.25);
-        out[1].v[v] = t8 + hjx;
-        out[2].v[v] = t8 - hjx;
-        out[3].v[v] = t8 + hjy;
-        out[4].v[v] = t8 - hjy;
-        out[5].v[v] = t8 + hjz;
-        out[6].v[v] = t8 - hjz;
+        T_.v[v] = T;
+        X_.v[v] = hjx;
+        Y_.v[v] = hjy;
+        Z_.v[v] = hjz;
         if constexpr (MODE != 0) {
             if (active) {
-                const real Told = c0.v[v] + a1.v[v] + a2.v[v] + o3.v[v] + o4.v[v] + o5.v[v] + o6.v[v];
-                const double dT = fabs((double)T - (double)Told);
+                const double dT = fabs((double)T - (double)P.told[v]);
                 const double qx = 0.5 * (double)jx + (double)hjx;
                 const double qy = 0.5 * (double)jy + (double)hjy;
                 const double qz = 0.5 * (double)jz + (double)hjz;
@@ -179,13 +319,14 @@ __device__ __forceinline__ void node_update(const Cell<real> &c, const real *__r
                 acc.v[R_QY] += qy;
                 acc.v[R_QZ] += qz;
                 acc.v[R_TSUM] += (double)T;
-                // rounding energy of this node: stored outputs minus the
-                // pulled inputs, both summed exactly in FP64 (the +-h
-                // shifts cancel within a node)
-                double din = (double)f0 + (double)r1 + (double)r2 + (double)r3 + (double)r4 + (double)r5 + (double)r6;
-                double dout = 0.0;
-#pragma unroll
-                for (int i = 0; i < Q; i++) dout += (double)out[i].v[v];
+                // rounding energy of this node: the populations the next step
+                // will stream minus the ones pulled now, both summed exactly
+                // in FP64 (the +-h shifts cancel within a node)
+                const double din = (double)f0 + (double)P.r[0][v] + (double)P.r[1][v] + (double)P.r[2][v] +
+                                   (double)P.r[3][v] + (double)P.r[4][v] + (double)P.r[5][v];
+                const double dout = (double)(T * real(0.25)) + (double)gplus(T, hjx) + (double)gminus(T, hjx) +
+                                    (double)gplus(T, hjy) + (double)gminus(T, hjy) + (double)gplus(T, hjz) +
+                                    (double)gminus(T, hjz);
                 acc.v[R_LEAK] += dout - din;
                 if (!(dT <= 1e300)) acc.v[R_NONFINITE] += 1.0;
                 else acc.v[R_RESID] = fmax(acc.v[R_RESID], dT);
@@ -198,34 +339,56 @@ __device__ __forceinline__ void node_update(const Cell<real> &c, const real *__r
             }
         }
     }
-
     if constexpr (MODE != 0) {
         if (active) {
             // wall link fluxes through the isothermal faces:
             // hot:  eps (T_hot - T_lin(0)) - 2 g_out = h - 2 g_out
             // cold: 2 g_out + eps (T_lin(n-1) - T_cold) = 2 g_out + h
-            const int g = c.gaxis;
-            const double hg = (double)c.h[g];
-            if (g == 0) {
-                if (x0 == 0) acc.v[R_PHI_HOT] += hg - 2.0 * (double)rawHotX;
-                if (x0 + VEC == nx) acc.v[R_PHI_COLD] += 2.0 * (double)rawColdX + hg;
-            } else if (g == 1) {
-                if (ylo) for (int v = 0; v < VEC; v++) acc.v[R_PHI_HOT] += hg - 2.0 * (double)b3.v[v];
-                if (yhi) for (int v = 0; v < VEC; v++) acc.v[R_PHI_COLD] += 2.0 * (double)b4.v[v] + hg;
-            } else {
-                if (zlo) for (int v = 0; v < VEC; v++) acc.v[R_PHI_HOT] += hg - 2.0 * (double)b5.v[v];
-                if (zhi) for (int v = 0; v < VEC; v++) acc.v[R_PHI_COLD] += 2.0 * (double)b6.v[v] + hg;
-            }
+            const double hg = (double)c.h[c.gaxis];
+            const double nodes = (c.gaxis == 0) ? 1.0 : (double)VEC;
+            if (P.hot) acc.v[R_PHI_HOT] += nodes * hg - 2.0 * P.out_hot;
+            if (P.cold) acc.v[R_PHI_COLD] += 2.0 * P.out_cold + nodes * hg;
         }
     }
-
     if constexpr (MODE <= 1) {
         if (active) {
             real *__restrict__ d = c.dst;
+            constexpr bool NS = (NT & 2) != 0;
+            if constexpr (STORAGE == 0) {
+                Vec<real, VEC> o;
 #pragma unroll
-            for (int i = 0; i < Q; i++) vstore<real, VEC, (NT & 2) != 0>(d + i * N + base, out[i]);
+                for (int v = 0; v < VEC; v++) o.v[v] = T_.v[v] * real(0.25);
+                vstore<real, VEC, NS>(d + base, o);
+#pragma unroll
+                for (int a = 0; a < 3; a++) {
+                    const Vec<real, VEC> &hj = (a == 0) ? X_ : ((a == 1) ? Y_ : Z_);
+                    Vec<real, VEC> p, m;
+#pragma unroll
+                    for (int v = 0; v < VEC; v++) {
+                        p.v[v] = gplus(T_.v[v], hj.v[v]);
+                        m.v[v] = gminus(T_.v[v], hj.v[v]);
+                    }
+                    vstore<real, VEC, NS>(d + (2 * a + 1) * N + base, p);
+                    vstore<real, VEC, NS>(d + (2 * a + 2) * N + base, m);
+                }
+            } else {
+                vstore<real, VEC, NS>(d + base, T_);
+                vstore<real, VEC, NS>(d + N + base, X_);
+                vstore<real, VEC, NS>(d + 2 * N + base, Y_);
+                vstore<real, VEC, NS>(d + 3 * N + base, Z_);
+            }
         }
     }
+}
+
+template <typename real, int VEC, int MODE, int NT = 0, int STORAGE = 0>
+__device__ __forceinline__ void node_update(const Cell<real> &c, const real *__restrict__ tab, int xv, int y, int z,
+                                            bool active, const XLink &xl, Acc &acc, real *__restrict__ qout,
+                                            real qscale) {
+    Pulled<real, VEC> P;
+    if constexpr (STORAGE == 0) pull_dist<real, VEC, MODE, NT>(c, xv, y, z, xl, P);
+    else pull_mom<real, VEC, MODE, NT>(c, xv, y, z, xl, P);
+    collide_store<real, VEC, MODE, NT, STORAGE>(c, tab, xv, y, z, active, P, acc, qout, qscale);
 }
 
 template <typename real>

@@ -30,11 +30,13 @@ struct Cell {
     real sgn[3];              // reflection sign on a wall: -1 isothermal, +1 adiabatic
     real h[3];                // shift of the gradient-axis populations (eps dT / (2 N_g)), else 0
     int gaxis;
+    int storage;              // 0: 7 populations [7][N]; 1: moments (T - T_lin, jhat/2) [4][N]
 };
 
 struct Launch {
     int vec, bx, by;
-    int nt;  // bit 0: non-temporal state loads, bit 1: non-temporal state stores
+    int nt;   // bit 0: non-temporal state loads, bit 1: non-temporal state stores
+    int map;  // 1: XCD-aware block order (each XCD sweeps one slab of rows)
 };
 
 // kernel launchers (lbm_kernels.hip)

@@ -50,26 +50,51 @@ __device__ __forceinline__ XLink chunk_links(const Cell<real> &c, int xv, int tx
     return xl;
 }
 
-template <typename real, int VEC, int NT>
+// Block coordinates.  With MAP the linear dispatch order (workgroups go to
+// the 8 XCDs round robin) is remapped so that each XCD sweeps one slab of
+// y-blocks through all planes: the rows and planes a block pulls from its
+// neighbours were then loaded by the same XCD moments before and are still in
+// its L2 (requires gridDim.y % 8 == 0).
+template <int MAP>
+__device__ __forceinline__ void block_coords(int &bxi, int &byi, int &bzi) {
+    if constexpr (MAP) {
+        const unsigned gx = gridDim.x, gy = gridDim.y;
+        const unsigned b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+        const unsigned slab = gy / 8, xcd = b % 8, seq = b / 8;
+        bxi = (int)(seq % gx);
+        const unsigned r = seq / gx;
+        byi = (int)(xcd * slab + r % slab);
+        bzi = (int)(r / slab);
+    } else {
+        bxi = blockIdx.x;
+        byi = blockIdx.y;
+        bzi = blockIdx.z;
+    }
+}
+
+template <typename real, int VEC, int NT, int ST, int MAP>
 __global__ void __launch_bounds__(256) k_step(Cell<real> c) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     real *tab = reinterpret_cast<real *>(smem_raw);
     load_table(c, tab);
+    int bxi, byi, bzi;
+    block_coords<MAP>(bxi, byi, bzi);
     const int tx = threadIdx.x, bx = blockDim.x;
-    int xv = blockIdx.x * bx + tx;
-    int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
+    int xv = bxi * bx + tx;
+    int y = byi * blockDim.y + threadIdx.y;
+    const int z = bzi;
     const bool active = (xv < c.nxv) && (y < c.ny);
     xv = min(xv, c.nxv - 1);
     y = min(y, c.ny - 1);
     Acc dummy;
-    node_update<real, VEC, 0, NT>(c, tab, xv, y, z, active, chunk_links<VEC>(c, xv, tx, bx), dummy, nullptr, real(0));
+    node_update<real, VEC, 0, NT, ST>(c, tab, xv, y, z, active, chunk_links<VEC>(c, xv, tx, bx), dummy, nullptr,
+                                      real(0));
 }
 
 // Observables (and optionally the step): the grid covers x and y like the
 // step kernel; each block walks `zper` consecutive planes so that the number
 // of partials stays small and the summation order is fixed.
-template <typename real, int VEC, int MODE>
+template <typename real, int VEC, int MODE, int ST>
 __global__ void __launch_bounds__(256) k_check(Cell<real> c, int zper, double *partials, real *qout, real qscale) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     real *tab = reinterpret_cast<real *>(smem_raw);
@@ -84,7 +109,7 @@ __global__ void __launch_bounds__(256) k_check(Cell<real> c, int zper, double *p
     acc.zero();
     const int z0 = blockIdx.z * zper, z1 = min(c.nz, z0 + zper);
     const XLink xl = chunk_links<VEC>(c, xv, tx, bx);
-    for (int z = z0; z < z1; z++) node_update<real, VEC, MODE>(c, tab, xv, y, z, active, xl, acc, qout, qscale);
+    for (int z = z0; z < z1; z++) node_update<real, VEC, MODE, 0, ST>(c, tab, xv, y, z, active, xl, acc, qout, qscale);
     const long long b = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
     block_reduce_store(acc, partials + b * NRED);
 }
@@ -153,10 +178,15 @@ __global__ void k_init(Cell<real> c, real *state, const real *t0, int flags, dou
             const double m[3][3] = {{tb[0], tb[3], tb[4]}, {tb[3], tb[1], tb[5]}, {tb[4], tb[5], tb[2]}};
             for (int a = 0; a < 3; a++) jh[a] = -0.25 * (m[a][0] * grad[0] + m[a][1] * grad[1] + m[a][2] * grad[2]);
         }
-        state[i] = (real)(0.25 * dev);
-        for (int a = 0; a < 3; a++) {
-            state[(2 * a + 1) * n + i] = (real)(0.125 * dev + 0.5 * jh[a]);
-            state[(2 * a + 2) * n + i] = (real)(0.125 * dev - 0.5 * jh[a]);
+        if (c.storage) {
+            state[i] = (real)dev;
+            for (int a = 0; a < 3; a++) state[(a + 1) * n + i] = (real)(0.5 * jh[a]);
+        } else {
+            state[i] = (real)(0.25 * dev);
+            for (int a = 0; a < 3; a++) {
+                state[(2 * a + 1) * n + i] = (real)(0.125 * dev + 0.5 * jh[a]);
+                state[(2 * a + 2) * n + i] = (real)(0.125 * dev - 0.5 * jh[a]);
+            }
         }
     }
 }
@@ -171,7 +201,8 @@ __global__ void k_temperature(Cell<real> c, const real *__restrict__ state, real
         const long long r = i / c.nx;
         const int pos[3] = {x, (int)(r % c.ny), (int)(r / c.ny)};
         real acc = state[i];
-        for (int q = 1; q < Q; q++) acc += state[q * n + i];
+        if (!c.storage)
+            for (int q = 1; q < Q; q++) acc += state[q * n + i];
         t_out[i] = (real)((double)acc + t_lin(pos[c.gaxis], ext[c.gaxis], t_hot, dT));
     }
 }
@@ -198,26 +229,37 @@ static inline dim3 step_grid(int nxv, int ny, int nz, const Launch &L) {
     return dim3((nxv + L.bx - 1) / L.bx, (ny + L.by - 1) / L.by, nz);
 }
 
+template <typename real, int ST, int MAP>
+static void launch_step_st(const Cell<real> &cc, const Launch &L, dim3 grid, dim3 block, size_t sh, hipStream_t s) {
+    switch (L.vec * 4 + (L.nt & 3)) {
+        case 16: hipLaunchKernelGGL((k_step<real, 4, 0, ST, MAP>), grid, block, sh, s, cc); break;
+        case 17: hipLaunchKernelGGL((k_step<real, 4, 1, ST, MAP>), grid, block, sh, s, cc); break;
+        case 18: hipLaunchKernelGGL((k_step<real, 4, 2, ST, MAP>), grid, block, sh, s, cc); break;
+        case 19: hipLaunchKernelGGL((k_step<real, 4, 3, ST, MAP>), grid, block, sh, s, cc); break;
+        case 8: hipLaunchKernelGGL((k_step<real, 2, 0, ST, MAP>), grid, block, sh, s, cc); break;
+        case 9: hipLaunchKernelGGL((k_step<real, 2, 1, ST, MAP>), grid, block, sh, s, cc); break;
+        case 10: hipLaunchKernelGGL((k_step<real, 2, 2, ST, MAP>), grid, block, sh, s, cc); break;
+        case 11: hipLaunchKernelGGL((k_step<real, 2, 3, ST, MAP>), grid, block, sh, s, cc); break;
+        case 4: hipLaunchKernelGGL((k_step<real, 1, 0, ST, MAP>), grid, block, sh, s, cc); break;
+        case 5: hipLaunchKernelGGL((k_step<real, 1, 1, ST, MAP>), grid, block, sh, s, cc); break;
+        case 6: hipLaunchKernelGGL((k_step<real, 1, 2, ST, MAP>), grid, block, sh, s, cc); break;
+        default: hipLaunchKernelGGL((k_step<real, 1, 3, ST, MAP>), grid, block, sh, s, cc); break;
+    }
+}
+
 template <typename real>
 hipError_t launch_step(const Cell<real> &c, const Launch &L, hipStream_t s) {
     Cell<real> cc = c;
     cc.nxv = c.nx / L.vec;
     const dim3 grid = step_grid(cc.nxv, c.ny, c.nz, L), block(L.bx, L.by);
     const size_t sh = sizeof(real) * TABW * c.nphase;
-    switch (L.vec * 4 + (L.nt & 3)) {
-        case 16: hipLaunchKernelGGL((k_step<real, 4, 0>), grid, block, sh, s, cc); break;
-        case 17: hipLaunchKernelGGL((k_step<real, 4, 1>), grid, block, sh, s, cc); break;
-        case 18: hipLaunchKernelGGL((k_step<real, 4, 2>), grid, block, sh, s, cc); break;
-        case 19: hipLaunchKernelGGL((k_step<real, 4, 3>), grid, block, sh, s, cc); break;
-        case 8: hipLaunchKernelGGL((k_step<real, 2, 0>), grid, block, sh, s, cc); break;
-        case 9: hipLaunchKernelGGL((k_step<real, 2, 1>), grid, block, sh, s, cc); break;
-        case 10: hipLaunchKernelGGL((k_step<real, 2, 2>), grid, block, sh, s, cc); break;
-        case 11: hipLaunchKernelGGL((k_step<real, 2, 3>), grid, block, sh, s, cc); break;
-        case 4: hipLaunchKernelGGL((k_step<real, 1, 0>), grid, block, sh, s, cc); break;
-        case 5: hipLaunchKernelGGL((k_step<real, 1, 1>), grid, block, sh, s, cc); break;
-        case 6: hipLaunchKernelGGL((k_step<real, 1, 2>), grid, block, sh, s, cc); break;
-        case 7: hipLaunchKernelGGL((k_step<real, 1, 3>), grid, block, sh, s, cc); break;
-        default: return hipErrorInvalidValue;
+    const bool map = L.map && (grid.y % 8 == 0);
+    if (cc.storage) {
+        if (map) launch_step_st<real, 1, 1>(cc, L, grid, block, sh, s);
+        else launch_step_st<real, 1, 0>(cc, L, grid, block, sh, s);
+    } else {
+        if (map) launch_step_st<real, 0, 1>(cc, L, grid, block, sh, s);
+        else launch_step_st<real, 0, 0>(cc, L, grid, block, sh, s);
     }
     return hipGetLastError();
 }
@@ -238,14 +280,21 @@ int check_blocks(const Cell<real> &c, const Launch &L) {
     return g.x * g.y * ((c.nz + zper - 1) / zper);
 }
 
+template <typename real, int VEC, int ST>
+static void launch_check_st(const Cell<real> &c, dim3 grid, dim3 block, size_t sh, int zper, int mode, double *parts,
+                            real *q, real qs, hipStream_t s) {
+    switch (mode) {
+        case 1: hipLaunchKernelGGL((k_check<real, VEC, 1, ST>), grid, block, sh, s, c, zper, parts, q, qs); break;
+        case 2: hipLaunchKernelGGL((k_check<real, VEC, 2, ST>), grid, block, sh, s, c, zper, parts, q, qs); break;
+        default: hipLaunchKernelGGL((k_check<real, VEC, 3, ST>), grid, block, sh, s, c, zper, parts, q, qs); break;
+    }
+}
+
 template <typename real, int VEC>
 static void launch_check_vec(const Cell<real> &c, dim3 grid, dim3 block, size_t sh, int zper, int mode, double *parts,
                              real *q, real qs, hipStream_t s) {
-    switch (mode) {
-        case 1: hipLaunchKernelGGL((k_check<real, VEC, 1>), grid, block, sh, s, c, zper, parts, q, qs); break;
-        case 2: hipLaunchKernelGGL((k_check<real, VEC, 2>), grid, block, sh, s, c, zper, parts, q, qs); break;
-        default: hipLaunchKernelGGL((k_check<real, VEC, 3>), grid, block, sh, s, c, zper, parts, q, qs); break;
-    }
+    if (c.storage) launch_check_st<real, VEC, 1>(c, grid, block, sh, zper, mode, parts, q, qs, s);
+    else launch_check_st<real, VEC, 0>(c, grid, block, sh, zper, mode, parts, q, qs, s);
 }
 
 template <typename real>

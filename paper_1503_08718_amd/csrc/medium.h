@@ -56,9 +56,10 @@ struct mrtlbm_medium {
     double *pinned = nullptr;  // host staging for reductions
     int device = 0;
     int cur = 0;               // state in bufA (0) or bufB (1)
+    int storage = 0;           // 0: 7 populations per node, 1: 4 moments per node
     long long steps = 0;
     bool initialised = false;
-    mrt::Launch launch{4, 64, 4, 0};
+    mrt::Launch launch{4, 64, 4, 0, 0};
     std::vector<mrt::GraphEntry> graphs;
 };
 

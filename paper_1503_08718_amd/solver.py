@@ -84,15 +84,21 @@ class Medium:
         self.grad_axis, self.t_hot, self.t_cold = int(grad_axis), float(t_hot), float(t_cold)
         return self
 
+    def set_storage(self, storage):
+        """"populations" (7 values per node) or "moments" (4 values per node)."""
+        v = {"populations": 0, "moments": 1, 0: 0, 1: 1}[storage]
+        check(load().mrtlbm_set_storage(self._h, v))
+        return self
+
     def set_scale(self, dmax: float):
         check(load().mrtlbm_set_scale(self._h, float(dmax)))
         return self
 
-    def set_launch(self, vec=None, bx=None, by=None, nt=0):
+    def set_launch(self, vec=None, bx=None, by=None, nt=0, map=0):
         if vec is None:
             check(load().mrtlbm_set_launch(self._h, None))
         else:
-            check(load().mrtlbm_set_launch(self._h, ctypes.byref(Launch(vec, bx, by, nt))))
+            check(load().mrtlbm_set_launch(self._h, ctypes.byref(Launch(vec, bx, by, nt, map))))
         return self
 
     def info(self) -> dict:
@@ -100,12 +106,12 @@ class Medium:
         n = ctypes.c_longlong()
         L = Launch()
         check(load().mrtlbm_info(self._h, ctypes.byref(s), ctypes.byref(n), ctypes.byref(L)))
-        return dict(scale=s.value, steps=n.value, launch=(L.vec, L.bx, L.by, L.nt))
+        return dict(scale=s.value, steps=n.value, launch=(L.vec, L.bx, L.by, L.nt, L.map))
 
     def autotune(self, cache_path: str | None = None):
         L = Launch()
         check(load().mrtlbm_autotune(self._h, cache_path.encode() if cache_path else None, ctypes.byref(L)))
-        return (L.vec, L.bx, L.by, L.nt)
+        return (L.vec, L.bx, L.by, L.nt, L.map)
 
     def load_tuned(self, cache_path: str) -> bool:
         st = check(load().mrtlbm_load_tuned(self._h, cache_path.encode()), allow=(0, 1))
@@ -152,13 +158,14 @@ class Medium:
         return out
 
     def state_get(self) -> torch.Tensor:
-        out = torch.empty((7,) + self.shape, dtype=self.dtype, device=self.device)
+        nv = load().mrtlbm_state_values(self._h)
+        out = torch.empty((nv,) + self.shape, dtype=self.dtype, device=self.device)
         check(load().mrtlbm_state_get(self._h, out.data_ptr()))
         return out
 
     def state_set(self, f: torch.Tensor, steps: int = 0):
         f = f.to(self.device, dtype=self.dtype).contiguous()
-        assert tuple(f.shape) == (7,) + self.shape
+        assert tuple(f.shape) == (load().mrtlbm_state_values(self._h),) + self.shape
         self._fset = f
         check(load().mrtlbm_state_set(self._h, f.data_ptr(), int(steps)))
         return self

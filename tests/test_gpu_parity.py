@@ -128,9 +128,10 @@ def test_flux_field_fp64(Medium):
 
 
 @pytest.mark.parametrize("launch", [(1, 16, 4), (2, 8, 8), (2, 32, 2), (4, 8, 16), (4, 64, 1), (1, 64, 4),
-                                    (4, 64, 4, 1), (4, 32, 8, 2), (2, 16, 16, 3)])
+                                    (4, 64, 4, 1), (4, 32, 8, 2), (2, 16, 16, 3), (4, 8, 8, 0, 1), (2, 16, 4, 3, 1)])
 def test_launch_shapes_bitwise_identical(Medium, launch):
-    m = w.random_medium(9, 32, 12, 6, 3)
+    # 64 rows: with by = 4 or 8 the number of row blocks is a multiple of 8, as the XCD remap needs
+    m = w.random_medium(9, 32, 64, 6, 3)
     ref, _ = pair(Medium, m, 1, (ADIABATIC, 0, PERIODIC))
     ref.step(40)
     g, _ = pair(Medium, m, 1, (ADIABATIC, 0, PERIODIC), launch=launch)
@@ -291,3 +292,67 @@ def test_max_steps_gives_partial_result(Medium):
     r = g.solve(1e-9, "keff", 300, check_every=100)
     assert r["status"] == "NOT_CONVERGED" and not r["converged"] and r["steps"] == 300
     assert r["keff_hot"] > r["keff_cold"]
+
+
+# ---------------------------------------------------------------------------
+# moment storage: 4 values per node, bit-identical evolution
+# ---------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("case", CASES[:5] + [(32, 16, 12, 5, 2, (PERIODIC, ADIABATIC, 0), 9)],
+                         ids=lambda c: "x".join(map(str, c[:3])) + f"_g{c[4]}")
+def test_moment_storage_bitwise_equals_populations(Medium, case, prec):
+    import torch
+
+    nx, ny, nz, nph, grad, sides, seed = case
+    m = w.random_medium(seed, nx, ny, nz, nph)
+    rng = np.random.default_rng(seed)
+    T0 = rng.uniform(-0.5, 1.5, m.phase.shape)
+    runs = []
+    for storage in ("populations", "moments"):
+        g = Medium(m.phase, m.k, precision=prec)
+        g.set_storage(storage)
+        g.set_bc(grad, 0.8, -0.4, [SIDE_NAMES[s] for s in sides])
+        g.init(T0, flux=True)
+        g.step(37)
+        runs.append((g.temperature(), g.flux(), g.keff(), g.solve(1e-30, "keff", 137, check_every=50)))
+    (ta, qa, ka, ra), (tb, qb, kb, rb) = runs
+    assert torch.equal(ta, tb)
+    assert torch.equal(qa, qb)
+    assert ka == kb and ra == rb
+
+
+def test_moment_storage_matches_oracle_and_resumes(Medium):
+    import torch
+
+    m = w.c1_layered(16)
+    g, o = pair(Medium, m, 0, (0, PERIODIC, PERIODIC))
+    g.set_storage("moments")
+    g.init()
+    g.step(250)
+    o.step(250)
+    assert field_err(g, o) < 1e-12
+    snap = g.state_get()
+    assert snap.shape[0] == 4
+    g.step(40)
+    h = Medium(m.phase, m.k, precision="f64").set_storage("moments").set_bc(0)
+    h.state_set(snap, steps=250)
+    h.step(40)
+    assert torch.equal(g.state_get(), h.state_get())
+
+
+def test_moment_storage_batch(Medium):
+    import torch
+
+    from paper_1503_08718_amd.solver import batch_solve
+
+    media = [w.braid(16, 16, 24, 25.0, 0.45), w.braid(24, 16, 16, 40.0, 0.55)]
+    a = [Medium(mm.phase, mm.k, precision="f32").set_storage("moments").set_bc(ax).init()
+         for mm, ax in zip(media, (2, 0))]
+    b = [Medium(mm.phase, mm.k, precision="f32").set_bc(ax).init() for mm, ax in zip(media, (2, 0))]
+    ra, _ = batch_solve(a, tol=1e-30, kind="keff", max_steps=400, check_every=100)
+    rb, _ = batch_solve(b, tol=1e-30, kind="keff", max_steps=400, check_every=100)
+    for x, y, p, q in zip(a, b, ra, rb):
+        assert torch.equal(x.temperature(), y.temperature())
+        assert p == q
