@@ -80,7 +80,9 @@ def parse():
     p.add_argument("--ref-tol", type=float, default=1e-7)
     p.add_argument("--no-ref", action="store_true")
     p.add_argument("--precision", default="", choices=["", "f32", "f64"], help="solve mode: one solve per axis")
-    p.add_argument("--start", default="zero", choices=["zero", "linear", "learned"])
+    p.add_argument("--start", default="zero",
+                   help="zero | linear | learned; sweep mode takes a comma list (e.g. zero,learned)")
+    p.add_argument("--ref-cells", type=int, default=0, help="sweep mode: FP64 reference for the first K cells")
     p.add_argument("--max-steps", type=int, default=20_000_000)
     p.add_argument("--cells", type=int, default=64)
     p.add_argument("--seed", type=int, default=1503)
@@ -288,44 +290,61 @@ def mode_solve(args):
 
 
 def mode_sweep(args):
+    """The parametric sweep: braided cells of uneven size, angle and yarn
+    fraction, x and z solves of every cell (z as the x solve of the cell with
+    x and z exchanged) in one batched run per start, each to k_eff at --tol.
+    Cells per hour count voxelisation, set-up (for the learned start: feature
+    resampling, inference and interpolation) and the solves; training is a
+    one-off and not counted.  With --ref-cells K the first K cells are also
+    solved in FP64 to tol/100 and every start's error is reported on them."""
+    import numpy as np
     import torch
 
     import workloads
-    from paper_1503_08718_amd.solver import batch_solve
+    from paper_1503_08718_amd import warmstart as ws
 
+    starts = [s for s in args.start.split(",") if s]
     t_start = time.perf_counter()
     specs = workloads.sweep_cells(args.seed, args.cells)
-    media = [workloads.braid(c["nx"], c["ny"], c["nz"], c["gamma"], c["v"]) for c in specs]
+    media = ws.generate_media(specs)
+    canon = [mm for m in media for mm in ws.canonical_media(m)]
     t_gen = time.perf_counter() - t_start
-    results = {}
-    steps = {}
-    for axis in [int(a) for a in args.axes.split(",")]:
-        cells = []
-        for m in media:
-            g = _medium(m, "f32", args)
-            g.set_bc(axis, 1.0, 0.0, ("periodic",) * 3)
-            g.init()
-            cells.append(g)
+    net = ws.Net.from_file(args.model, batch=1) if ("learned" in starts or args.ref_cells) else None
+    out = {"mode": "sweep", "cells": len(media), "solves_per_cell": 2, "tol": args.tol, "storage": args.storage,
+           "nodes_total": int(sum(m.phase.size for m in media)), "seconds_geometry": round(t_gen, 2),
+           "sizes": [list(m.phase.shape[::-1]) for m in media]}
+    ref = None
+    if args.ref_cells:
+        sub = canon[:2 * args.ref_cells]
+        _, rres, _, _ = ws.solve_fields(sub, tol=args.tol / 100, start="learned", net=net, batch=True,
+                                        precision="f64", max_steps=args.max_steps, keep_fields=False)
+        ref = [r["keff"] for r in rres]
+        out["reference"] = {"cells": args.ref_cells, "precision": "f64", "tol": args.tol / 100,
+                            "all_converged": all(r["converged"] for r in rres), "keff": [round(k, 7) for k in ref]}
+        print(json.dumps({"reference": "done", "cells": args.ref_cells}), flush=True)
+    for start in starts:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res, st = batch_solve(cells, tol=args.tol, kind="keff", max_steps=args.max_steps, check_every=1000)
+        _, res, setup, fb = ws.solve_fields(canon, tol=args.tol, start=start, net=net, batch=True,
+                                            max_steps=args.max_steps, storage=args.storage, keep_fields=False)
         torch.cuda.synchronize()
-        results[axis] = (res, st, time.perf_counter() - t0)
-        steps[axis] = [r["steps"] for r in res]
-        print(json.dumps({"axis": "xyz"[axis], "status": st, "seconds": round(results[axis][2], 2)}), flush=True)
-        del cells
-    wall = time.perf_counter() - t_start
-    conv = all(r["converged"] for res, _, _ in results.values() for r in res)
-    nodes = sum(m.phase.size for m in media)
-    lu = sum(m.phase.size * s for axis in steps for m, s in zip(media, steps[axis]))
-    return {"mode": "sweep", "cells": len(media), "nodes_total": nodes, "all_converged": conv,
-            "tol": args.tol, "axes": args.axes, "seconds_total": round(wall, 2),
-            "seconds_geometry": round(t_gen, 2),
-            "seconds_per_axis": {"xyz"[a]: round(v[2], 2) for a, v in results.items()},
-            "cells_per_hour": round(len(media) / (wall / 3600.0), 1),
-            "effective_MLUPS": round(lu / sum(v[2] for v in results.values()) / 1e6, 1),
-            "steps_per_cell": {"xyz"[a]: [min(s), max(s)] for a, s in steps.items()},
-            "keff": {"xyz"[a]: [round(r["keff"], 6) for r in v[0]] for a, v in results.items()}}
+        wall = time.perf_counter() - t0
+        steps = [r["steps"] for r in res]
+        lu = sum(m.phase.size * st for m, st in zip(canon, steps))
+        rec = {"all_converged": all(r["converged"] for r in res), "fallbacks": fb,
+               "seconds": round(wall, 2), "setup_seconds": round(setup, 2),
+               "cells_per_hour": round(len(media) / ((t_gen + wall) / 3600.0), 1),
+               "steps_mean": float(np.mean(steps)), "steps_min_max": [min(steps), max(steps)],
+               "effective_MLUPS": round(lu / max(wall - setup, 1e-9) / 1e6, 1),
+               "k_T": [round(r["keff"], 6) for r in res[0::2]], "k_L": [round(r["keff"], 6) for r in res[1::2]]}
+        if ref is not None:
+            errs = [abs(r["keff"] - k) / abs(k) for r, k in zip(res, ref)]
+            rec["max_rel_err_vs_reference"] = float(max(errs))
+            rec["mean_rel_err_vs_reference"] = float(np.mean(errs))
+        out[start] = rec
+        print(json.dumps({"start": start, "seconds": rec["seconds"], "steps_mean": rec["steps_mean"],
+                          "cells_per_hour": rec["cells_per_hour"], "fallbacks": fb}), flush=True)
+    return out
 
 
 PAPER_TABLE3 = {  # interior braiding angle, fibre fraction -> (k_T, k_L), the paper's predictions (Table III)

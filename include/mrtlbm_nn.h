@@ -91,17 +91,36 @@ mrtlbm_status mrtlbm_nn_to_bf16(const float *a, long long count, void *out, void
 mrtlbm_status mrtlbm_nn_features(const unsigned char *phase, int d, int h, int w, const float *feat6, void *out,
                                  void *stream);
 
+/* Host: per-phase network features of a medium sampled with voxel spacing
+ * spacing[3] (x, y, z) relative to the network grid.  Each tensor k6[p]
+ * (xx, yy, zz, xy, xz, yz) becomes K'_ab = K_ab / (spacing_a spacing_b) --
+ * the conductivity that gives the same steady equation after the change of
+ * variables x_a = spacing_a x'_a -- and all are divided by the largest
+ * eigenvalue over the phases.  out: FP32 [nphase][6], host memory.
+ * Errors: E_ARG, E_TENSOR (a transformed tensor not positive definite). */
+mrtlbm_status mrtlbm_nn_feature_table(const double *k6, int nphase, const double *spacing, float *out);
+
+/* Network input on a (dc, hc, wc) grid for a medium of (d, h, w) voxels with
+ * its gradient along x: out [dc][hc][wc][8] BF16; channels 0..5 = mean of
+ * feat6[phase] over the voxels whose centres lie in the coarse voxel (the
+ * voxel under its centre when there are none), channel 6 = (x + 1/2)/wc - 1/2
+ * of the coarse voxel, channel 7 = 0.  Equal sizes give mrtlbm_nn_features. */
+mrtlbm_status mrtlbm_nn_features_resampled(const unsigned char *phase, int d, int h, int w, const float *feat6, int dc,
+                                           int hc, int wc, void *out, void *stream);
+
 /* Training target: out = scale * (T - T_lin(x)), T_lin = 1 - (x + 1/2)/w. */
 mrtlbm_status mrtlbm_nn_target(const float *t, int d, int h, int w, float scale, float *out, void *stream);
 
-/* Start field from a prediction made on a grid f times coarser per axis:
- * trilinear interpolation of channel 0 of pred [dc][hc][wc][cpred] (periodic
- * in y and z, clamped in x), T = T_lin(x) + value / scale on the fine grid
- * [f dc][f hc][f wc].  *bad_host = number of values that are not finite or
- * lie outside [-margin, 1 + margin] (the caller falls back to another start
- * when it is not 0).  bad_scratch: 2048 ints.  Synchronises. */
-mrtlbm_status mrtlbm_nn_to_temperature(const float *pred, int cpred, int dc, int hc, int wc, int f, float scale,
-                                       float margin, float *t, int *bad_scratch, long long *bad_host, void *stream);
+/* Start field on the medium's (d, h, w) grid from a prediction made on a
+ * (dc, hc, wc) grid spanning the same cell: trilinear interpolation of
+ * channel 0 of pred [dc][hc][wc][cpred] between coarse voxel centres
+ * (periodic in y and z, clamped in x), T = T_lin(x) + value / scale.
+ * *bad_host = number of values that are not finite or lie outside
+ * [-margin, 1 + margin] (the caller falls back to another start when it is
+ * not 0).  bad_scratch: 2048 ints.  Synchronises. */
+mrtlbm_status mrtlbm_nn_to_temperature(const float *pred, int cpred, int dc, int hc, int wc, int d, int h, int w,
+                                       float scale, float margin, float *t, int *bad_scratch, long long *bad_host,
+                                       void *stream);
 
 #ifdef __cplusplus
 }

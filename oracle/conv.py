@@ -96,6 +96,53 @@ def up2_backward(dy):
     return dy.reshape(n, D // 2, 2, H // 2, 2, W // 2, 2, c).sum(axis=(2, 4, 6))
 
 
+def box_resample(x, shape):
+    """Resample x[D, H, W, C] to a (Dc, Hc, Wc) grid spanning the same box.
+
+    Fine voxel i of n along an axis has its centre at (i + 1/2)/n of the box
+    and belongs to coarse voxel floor((i + 1/2) nc / n); each coarse voxel is
+    the mean of its fine voxels, or, when it has none (refinement), the fine
+    voxel under its own centre."""
+    D, H, W, C = x.shape
+    out = np.zeros(tuple(shape) + (C,))
+    owner = [[(2 * i + 1) * nc // (2 * n) for i in range(n)] for n, nc in zip((D, H, W), shape)]
+    for cz in range(shape[0]):
+        zs = [i for i in range(D) if owner[0][i] == cz] or [(2 * cz + 1) * D // (2 * shape[0])]
+        for cy in range(shape[1]):
+            ys = [i for i in range(H) if owner[1][i] == cy] or [(2 * cy + 1) * H // (2 * shape[1])]
+            for cx in range(shape[2]):
+                xs = [i for i in range(W) if owner[2][i] == cx] or [(2 * cx + 1) * W // (2 * shape[2])]
+                out[cz, cy, cx] = x[np.ix_(zs, ys, xs)].reshape(-1, C).mean(axis=0)
+    return out
+
+
+def interp_to_fine(p, shape):
+    """Trilinear interpolation of p[Dc, Hc, Wc] at the voxel centres of a
+    (D, H, W) grid spanning the same box.  A fine centre sits at coarse
+    coordinate (i + 1/2) nc / n - 1/2 (coarse centres at integers); y and z
+    wrap periodically, x is clamped to the first and last coarse centre."""
+    Dc, Hc, Wc = p.shape
+    D, H, W = shape
+    out = np.zeros(shape)
+    for z in range(D):
+        for y in range(H):
+            for x in range(W):
+                c = [(x + 0.5) * Wc / W - 0.5, (y + 0.5) * Hc / H - 0.5, (z + 0.5) * Dc / D - 0.5]
+                base = [int(np.floor(v)) for v in c]
+                t = [v - b for v, b in zip(c, base)]
+                acc = 0.0
+                for dz in (0, 1):
+                    for dy in (0, 1):
+                        for dx in (0, 1):
+                            ix = min(max(base[0] + dx, 0), Wc - 1)
+                            iy = (base[1] + dy) % Hc
+                            iz = (base[2] + dz) % Dc
+                            wgt = (t[0] if dx else 1 - t[0]) * (t[1] if dy else 1 - t[1]) * (t[2] if dz else 1 - t[2])
+                            acc += wgt * p[iz, iy, ix]
+                out[z, y, x] = acc
+    return out
+
+
 def mse(pred, target):
     d = np.asarray(pred, np.float64) - np.asarray(target, np.float64)
     return float((d * d).mean()), 2.0 * d / d.size

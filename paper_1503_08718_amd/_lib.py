@@ -140,7 +140,10 @@ def load():
         "mrtlbm_nn_to_bf16": (I, [P, LL, P, P]),
         "mrtlbm_nn_features": (I, [P, I, I, I, P, P, P]),
         "mrtlbm_nn_target": (I, [P, I, I, I, F, P, P]),
-        "mrtlbm_nn_to_temperature": (I, [P, I, I, I, I, I, F, F, P, P, ctypes.POINTER(ctypes.c_longlong), P]),
+        "mrtlbm_nn_to_temperature": (I, [P, I, I, I, I, I, I, I, F, F, P, P, ctypes.POINTER(ctypes.c_longlong), P]),
+        "mrtlbm_nn_feature_table": (I, [ctypes.POINTER(ctypes.c_double), I, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_float)]),
+        "mrtlbm_nn_features_resampled": (I, [P, I, I, I, P, I, I, I, P, P]),
     })
     del FP
     sig["mrtlbm_set_progress"] = (None, [PROGRESS_FN, P, D])

@@ -78,7 +78,7 @@ void mrt::progress(const char *fmt, ...) {
 // ---------------------------------------------------------------------------
 
 // symmetric (xx, yy, zz, xy, xz, yz) -> row-major 3x3
-static void sym_full(const double *k6, double *m) {
+void mrt::sym_full(const double *k6, double *m) {
     m[0] = k6[0]; m[4] = k6[1]; m[8] = k6[2];
     m[1] = m[3] = k6[3];
     m[2] = m[6] = k6[4];
@@ -86,7 +86,7 @@ static void sym_full(const double *k6, double *m) {
 }
 
 // eigenvalues of a symmetric 3x3 (trigonometric solution of the cubic)
-static void sym_eig(const double *m, double ev[3]) {
+void mrt::sym_eig(const double *m, double ev[3]) {
     const double p1 = m[1] * m[1] + m[2] * m[2] + m[5] * m[5];
     const double q = (m[0] + m[4] + m[8]) / 3.0;
     if (p1 == 0.0) {
@@ -108,7 +108,7 @@ static void sym_eig(const double *m, double ev[3]) {
 }
 
 // positive definite by Sylvester's criterion (leading minors)
-static bool sym_pd(const double *m) {
+bool mrt::sym_pd(const double *m) {
     const double d1 = m[0];
     const double d2 = m[0] * m[4] - m[1] * m[3];
     const double d3 = m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) +

@@ -9,6 +9,12 @@
 
 #include "lbm_internal.h"
 
+// Every kernel that includes this file must perform exactly the same
+// floating-point operations per node (population vs moment storage, single
+// vs batched launches, any block shape), so the compiler may not fuse a
+// multiply and an add on its own; the fused operations are written out.
+#pragma clang fp contract(off)
+
 namespace mrt {
 
 
@@ -191,9 +197,9 @@ __device__ __forceinline__ void pull_dist(const Cell<real> &c, int xv, int y, in
 // very operations that produced them in distribution storage, so both
 // storages evolve bit for bit alike.
 template <typename real>
-__device__ __forceinline__ real gplus(real T, real z) { return T * real(0.125) + z; }
+__device__ __forceinline__ real gplus(real T, real z) { return fma(T, real(0.125), z); }
 template <typename real>
-__device__ __forceinline__ real gminus(real T, real z) { return T * real(0.125) - z; }
+__device__ __forceinline__ real gminus(real T, real z) { return fma(T, real(0.125), -z); }
 
 template <typename real, int VEC, int MODE, int NT>
 __device__ __forceinline__ void pull_mom(const Cell<real> &c, int xv, int y, int z, const XLink &xl,
@@ -302,9 +308,9 @@ __device__ __forceinline__ void collide_store(const Cell<real> &c, const real *_
         const real T = f0 + f1 + f2 + f3 + f4 + f5 + f6;
         const real jx = f1 - f2, jy = f3 - f4, jz = f5 - f6;
         const real *tb = tab + P.ph[v] * TABW;  // half of (I - tau^-1)
-        const real hjx = tb[0] * jx + tb[3] * jy + tb[4] * jz;
-        const real hjy = tb[3] * jx + tb[1] * jy + tb[5] * jz;
-        const real hjz = tb[4] * jx + tb[5] * jy + tb[2] * jz;
+        const real hjx = fma(tb[4], jz, fma(tb[3], jy, tb[0] * jx));
+        const real hjy = fma(tb[5], jz, fma(tb[1], jy, tb[3] * jx));
+        const real hjz = fma(tb[2], jz, fma(tb[5], jy, tb[4] * jx));
         T_.v[v] = T;
         X_.v[v] = hjx;
         Y_.v[v] = hjy;

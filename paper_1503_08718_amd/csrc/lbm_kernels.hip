@@ -178,14 +178,19 @@ __global__ void k_init(Cell<real> c, real *state, const real *t0, int flags, dou
             const double m[3][3] = {{tb[0], tb[3], tb[4]}, {tb[3], tb[1], tb[5]}, {tb[4], tb[5], tb[2]}};
             for (int a = 0; a < 3; a++) jh[a] = -0.25 * (m[a][0] * grad[0] + m[a][1] * grad[1] + m[a][2] * grad[2]);
         }
+        // round the moments (T - T_lin, jhat / 2) once to the storage
+        // precision; the populations are built from those rounded moments
+        // exactly as a collision builds them, so both storages start alike
+        const real Tr = (real)dev;
         if (c.storage) {
-            state[i] = (real)dev;
+            state[i] = Tr;
             for (int a = 0; a < 3; a++) state[(a + 1) * n + i] = (real)(0.5 * jh[a]);
         } else {
-            state[i] = (real)(0.25 * dev);
+            state[i] = Tr * real(0.25);
             for (int a = 0; a < 3; a++) {
-                state[(2 * a + 1) * n + i] = (real)(0.125 * dev + 0.5 * jh[a]);
-                state[(2 * a + 2) * n + i] = (real)(0.125 * dev - 0.5 * jh[a]);
+                const real zr = (real)(0.5 * jh[a]);
+                state[(2 * a + 1) * n + i] = gplus(Tr, zr);
+                state[(2 * a + 2) * n + i] = gminus(Tr, zr);
             }
         }
     }
@@ -200,9 +205,21 @@ __global__ void k_temperature(Cell<real> c, const real *__restrict__ state, real
         const int x = (int)(i % c.nx);
         const long long r = i / c.nx;
         const int pos[3] = {x, (int)(r % c.ny), (int)(r / c.ny)};
-        real acc = state[i];
-        if (!c.storage)
+        // T = sum of the seven populations, in the same order for both
+        // storages (moment storage rebuilds each population first)
+        real acc;
+        if (!c.storage) {
+            acc = state[i];
             for (int q = 1; q < Q; q++) acc += state[q * n + i];
+        } else {
+            const real T = state[i];
+            acc = T * real(0.25);
+            for (int a = 1; a < 4; a++) {
+                const real z = state[a * n + i];
+                acc += gplus(T, z);
+                acc += gminus(T, z);
+            }
+        }
         t_out[i] = (real)((double)acc + t_lin(pos[c.gaxis], ext[c.gaxis], t_hot, dT));
     }
 }

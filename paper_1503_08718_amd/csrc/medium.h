@@ -29,6 +29,11 @@ mrtlbm_status fail(mrtlbm_status st, const char *fmt, ...);
 void progress(const char *fmt, ...);
 mrtlbm_status hip_fail(hipError_t e, const char *what);
 size_t partial_capacity(int nx, int ny);
+// symmetric 3x3 helpers: (xx, yy, zz, xy, xz, yz) -> row-major 3x3; its
+// eigenvalues (trigonometric solution of the cubic); positive definiteness
+void sym_full(const double *k6, double *m);
+void sym_eig(const double *m, double ev[3]);
+bool sym_pd(const double *m);
 
 }  // namespace mrt
 

@@ -1,6 +1,8 @@
 // C ABI of the warm-start network layers (include/mrtlbm_nn.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <vector>
 
@@ -126,26 +128,57 @@ extern "C" mrtlbm_status mrtlbm_nn_features(const unsigned char *phase, int d, i
     return ret(nn_features(phase, d, h, w, feat6, out, (hipStream_t)stream), "features");
 }
 
+extern "C" mrtlbm_status mrtlbm_nn_feature_table(const double *k6, int nphase, const double *spacing, float *out) {
+    if (!k6 || !spacing || !out || nphase < 1 || nphase > 256) return fail(MRTLBM_E_ARG, "feature_table: bad arguments");
+    for (int a = 0; a < 3; a++)
+        if (!(spacing[a] > 0.0) || !std::isfinite(spacing[a])) return fail(MRTLBM_E_ARG, "feature_table: bad spacing");
+    // change of variables x_a = spacing_a x'_a turns div(K grad T) = 0 into
+    // the same equation in x' with K'_ab = K_ab / (spacing_a spacing_b)
+    static const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+    std::vector<double> kt(6 * (size_t)nphase);
+    double kmax = 0.0;
+    for (int p = 0; p < nphase; p++) {
+        double m[9], ev[3];
+        for (int c = 0; c < 6; c++) kt[6 * p + c] = k6[6 * p + c] / (spacing[ia[c]] * spacing[ib[c]]);
+        sym_full(&kt[6 * p], m);
+        if (!sym_pd(m)) return fail(MRTLBM_E_TENSOR, "feature_table: tensor of phase %d is not positive definite", p);
+        sym_eig(m, ev);
+        kmax = std::max(kmax, std::max(ev[0], std::max(ev[1], ev[2])));
+    }
+    for (size_t i = 0; i < kt.size(); i++) out[i] = (float)(kt[i] / kmax);
+    return MRTLBM_OK;
+}
+
+extern "C" mrtlbm_status mrtlbm_nn_features_resampled(const unsigned char *phase, int d, int h, int w,
+                                                      const float *feat6, int dc, int hc, int wc, void *out,
+                                                      void *stream) {
+    if (!phase || !feat6 || !out || d < 1 || h < 1 || w < 1 || dc < 1 || hc < 1 || wc < 1)
+        return fail(MRTLBM_E_ARG, "features_resampled: bad arguments");
+    return ret(nn_features_resampled(phase, d, h, w, feat6, dc, hc, wc, out, (hipStream_t)stream),
+               "features_resampled");
+}
+
 extern "C" mrtlbm_status mrtlbm_nn_target(const float *t, int d, int h, int w, float scale, float *out, void *stream) {
     if (!t || !out || d < 1 || h < 1 || w < 1) return fail(MRTLBM_E_ARG, "target: bad arguments");
     return ret(nn_target(t, d, h, w, scale, out, (hipStream_t)stream), "target");
 }
 
-extern "C" mrtlbm_status mrtlbm_nn_to_temperature(const float *pred, int cpred, int dc, int hc, int wc, int f,
-                                                  float scale, float margin, float *t, int *bad_scratch,
+extern "C" mrtlbm_status mrtlbm_nn_to_temperature(const float *pred, int cpred, int dc, int hc, int wc, int d, int h,
+                                                  int w, float scale, float margin, float *t, int *bad_scratch,
                                                   long long *bad_host, void *stream) {
-    if (!pred || !t || !bad_scratch || !bad_host || cpred < 1 || dc < 1 || hc < 1 || wc < 1 || f < 1 || scale == 0.0f)
+    if (!pred || !t || !bad_scratch || !bad_host || cpred < 1 || dc < 1 || hc < 1 || wc < 1 || d < 1 || h < 1 ||
+        w < 1 || scale == 0.0f)
         return fail(MRTLBM_E_ARG, "to_temperature: bad arguments");
     hipStream_t s = (hipStream_t)stream;
-    const long long n = (long long)dc * hc * wc * f * f * f;
+    const long long n = (long long)d * h * w;
     const int nb = nn_temp_blocks(n);
-    hipError_t e = nn_to_temperature(pred, cpred, dc, hc, wc, f, scale, margin, t, bad_scratch, s);
-    std::vector<int> h(nb);
-    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), bad_scratch, nb * sizeof(int), hipMemcpyDeviceToHost, s);
+    hipError_t e = nn_to_temperature(pred, cpred, dc, hc, wc, d, h, w, scale, margin, t, bad_scratch, s);
+    std::vector<int> counts(nb);
+    if (e == hipSuccess) e = hipMemcpyAsync(counts.data(), bad_scratch, nb * sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "to_temperature");
     long long bad = 0;
-    for (int v : h) bad += v;
+    for (int v : counts) bad += v;
     *bad_host = bad;
     return MRTLBM_OK;
 }

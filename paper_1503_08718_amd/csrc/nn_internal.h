@@ -29,10 +29,12 @@ hipError_t nn_adam(float *w, const float *g, float *m, float *v, long long n, fl
                    int t, void *wb, hipStream_t s);
 hipError_t nn_to_bf16(const float *a, long long n, void *out, hipStream_t s);
 hipError_t nn_features(const uint8_t *phase, int D, int H, int W, const float *feat, void *out, hipStream_t s);
+hipError_t nn_features_resampled(const uint8_t *phase, int D, int H, int W, const float *feat, int Dc, int Hc, int Wc,
+                                 void *out, hipStream_t s);
 hipError_t nn_target(const float *T, int D, int H, int W, float scale, float *out, hipStream_t s);
 int nn_temp_blocks(long long n);
-hipError_t nn_to_temperature(const float *pred, int cpred, int Dc, int Hc, int Wc, int f, float scale, float margin,
-                             float *T, int *bad, hipStream_t s);
+hipError_t nn_to_temperature(const float *pred, int cpred, int Dc, int Hc, int Wc, int D, int H, int W, float scale,
+                             float margin, float *T, int *bad, hipStream_t s);
 // loss = scale * fixed-order sum of p[0 .. rows)
 hipError_t nn_sum_rows(const float *p, int rows, float scale, float *out, hipStream_t s);
 }  // namespace mrt

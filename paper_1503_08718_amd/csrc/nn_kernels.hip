@@ -340,6 +340,47 @@ __global__ void k_features(const uint8_t *__restrict__ phase, int D, int H, int 
     }
 }
 
+// first fine index of coarse cell c when n fine voxels are resampled to nc:
+// fine voxel i belongs to the coarse cell that holds its centre, i.e. to
+// floor((2i + 1) nc / (2n)); the first i of cell c solves (2i + 1) nc >= 2 c n
+__device__ __forceinline__ int box_lo(int c, int n, int nc) {
+    const long long num = 2LL * c * n - nc;
+    return num <= 0 ? 0 : (int)((num + 2LL * nc - 1) / (2LL * nc));
+}
+
+// Network input on a coarse grid (Dc, Hc, Wc) for a medium of (D, H, W)
+// voxels: channels 0..5 average feat[phase] over the fine voxels whose
+// centres lie in the coarse voxel (a coarse voxel with none, when the grid
+// is refined, takes the fine voxel under its centre), channel 6 is the
+// coarse voxel's own x coordinate, channel 7 is zero.
+__global__ void k_features_resampled(const uint8_t *__restrict__ phase, int D, int H, int W,
+                                     const float *__restrict__ feat, int Dc, int Hc, int Wc, bf16 *__restrict__ out) {
+    const long long total = (long long)Dc * Hc * Wc;
+    for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < total; v += (long long)gridDim.x * blockDim.x) {
+        const int cx = (int)(v % Wc);
+        const long long r = v / Wc;
+        const int cy = (int)(r % Hc), cz = (int)(r / Hc);
+        int x0 = box_lo(cx, W, Wc), x1 = box_lo(cx + 1, W, Wc);
+        int y0 = box_lo(cy, H, Hc), y1 = box_lo(cy + 1, H, Hc);
+        int z0 = box_lo(cz, D, Dc), z1 = box_lo(cz + 1, D, Dc);
+        if (x1 <= x0) { x0 = (int)(((2LL * cx + 1) * W) / (2LL * Wc)); x1 = x0 + 1; }
+        if (y1 <= y0) { y0 = (int)(((2LL * cy + 1) * H) / (2LL * Hc)); y1 = y0 + 1; }
+        if (z1 <= z0) { z0 = (int)(((2LL * cz + 1) * D) / (2LL * Dc)); z1 = z0 + 1; }
+        float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int z = z0; z < z1; z++)
+            for (int y = y0; y < y1; y++)
+                for (int x = x0; x < x1; x++) {
+                    const float *f = feat + 6 * phase[((long long)z * H + y) * W + x];
+                    for (int c = 0; c < 6; c++) acc[c] += f[c];
+                }
+        const float inv = 1.0f / (float)((z1 - z0) * (y1 - y0) * (x1 - x0));
+        bf16 *o = out + v * 8;
+        for (int c = 0; c < 6; c++) o[c] = (bf16)(acc[c] * inv);
+        o[6] = (bf16)(((float)cx + 0.5f) / (float)Wc - 0.5f);
+        o[7] = (bf16)0.0f;
+    }
+}
+
 // training target: scale * (T - T_lin(x)), T_lin = 1 - (x + 1/2) / W (walls 1 -> 0)
 __global__ void k_target(const float *__restrict__ T, int D, int H, int W, float scale, float *__restrict__ out) {
     const long long total = (long long)D * H * W;
@@ -349,22 +390,23 @@ __global__ void k_target(const float *__restrict__ T, int D, int H, int W, float
     }
 }
 
-// Temperature start field from a prediction on a grid f times coarser per
-// axis (pred[v][cpred], channel 0 = scale * (T - T_lin)): trilinear
-// interpolation between coarse voxel centres (periodic in y and z, clamped
-// in x), then T = T_lin(x) + pred / scale.  bad[0] counts values that are not
-// finite or outside [-margin, 1 + margin].
-__global__ void k_to_temperature(const float *__restrict__ pred, int cpred, int Dc, int Hc, int Wc, int f, float scale,
-                                 float margin, float *__restrict__ T, int *__restrict__ bad) {
-    const int D = Dc * f, H = Hc * f, W = Wc * f;
+// Temperature start field on a (D, H, W) grid from a prediction on a
+// (Dc, Hc, Wc) grid covering the same cell (pred[v][cpred], channel 0 =
+// scale * (T - T_lin)): trilinear interpolation between coarse voxel centres
+// (periodic in y and z, clamped in x), then T = T_lin(x) + pred / scale.
+// bad[block] counts values that are not finite or outside [-margin, 1 + margin].
+__global__ void k_to_temperature(const float *__restrict__ pred, int cpred, int Dc, int Hc, int Wc, int D, int H, int W,
+                                 float scale, float margin, float *__restrict__ T, int *__restrict__ bad) {
     const long long total = (long long)D * H * W;
+    const float rx = (float)Wc / (float)W, ry = (float)Hc / (float)H, rz = (float)Dc / (float)D;
     int nbad = 0;
     for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < total; v += (long long)gridDim.x * blockDim.x) {
         const int x = (int)(v % W);
         const long long r = v / W;
         const int y = (int)(r % H), z = (int)(r / H);
         // fine voxel centre in coarse-voxel-centre coordinates
-        const float cx = ((float)x + 0.5f) / f - 0.5f, cy = ((float)y + 0.5f) / f - 0.5f, cz = ((float)z + 0.5f) / f - 0.5f;
+        const float cx = ((float)x + 0.5f) * rx - 0.5f, cy = ((float)y + 0.5f) * ry - 0.5f,
+                    cz = ((float)z + 0.5f) * rz - 0.5f;
         const float fx = floorf(cx), fy = floorf(cy), fz = floorf(cz);
         const float tx = cx - fx, ty = cy - fy, tz = cz - fz;
         float acc = 0.0f;
@@ -507,6 +549,13 @@ hipError_t nn_features(const uint8_t *phase, int D, int H, int W, const float *f
     return hipGetLastError();
 }
 
+hipError_t nn_features_resampled(const uint8_t *phase, int D, int H, int W, const float *feat, int Dc, int Hc, int Wc,
+                                 void *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_features_resampled, dim3(g1((long long)Dc * Hc * Wc)), dim3(256), 0, s, phase, D, H, W, feat,
+                       Dc, Hc, Wc, (bf16 *)out);
+    return hipGetLastError();
+}
+
 hipError_t nn_target(const float *T, int D, int H, int W, float scale, float *out, hipStream_t s) {
     hipLaunchKernelGGL(k_target, dim3(g1((long long)D * H * W)), dim3(256), 0, s, T, D, H, W, scale, out);
     return hipGetLastError();
@@ -514,11 +563,11 @@ hipError_t nn_target(const float *T, int D, int H, int W, float scale, float *ou
 
 int nn_temp_blocks(long long n) { return g1(n) > 2048 ? 2048 : g1(n); }
 
-hipError_t nn_to_temperature(const float *pred, int cpred, int Dc, int Hc, int Wc, int f, float scale, float margin,
-                             float *T, int *bad, hipStream_t s) {
-    const long long n = (long long)Dc * Hc * Wc * f * f * f;
-    hipLaunchKernelGGL(k_to_temperature, dim3(nn_temp_blocks(n)), dim3(256), 0, s, pred, cpred, Dc, Hc, Wc, f, scale,
-                       margin, T, bad);
+hipError_t nn_to_temperature(const float *pred, int cpred, int Dc, int Hc, int Wc, int D, int H, int W, float scale,
+                             float margin, float *T, int *bad, hipStream_t s) {
+    const long long n = (long long)D * H * W;
+    hipLaunchKernelGGL(k_to_temperature, dim3(nn_temp_blocks(n)), dim3(256), 0, s, pred, cpred, Dc, Hc, Wc, D, H, W,
+                       scale, margin, T, bad);
     return hipGetLastError();
 }
 

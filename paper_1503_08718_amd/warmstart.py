@@ -57,11 +57,17 @@ def canonical_media(m):
     return m, m.permuted((2, 1, 0))
 
 
-def feature_table(k6: np.ndarray) -> np.ndarray:
-    """Per-phase input features: the tensor entries over the largest eigenvalue."""
-    kmax = max(np.linalg.eigvalsh(np.array([[r[0], r[3], r[4]], [r[3], r[1], r[5]], [r[4], r[5], r[2]]])).max()
-               for r in k6)
-    return (np.asarray(k6, np.float64) / kmax).astype(np.float32)
+def feature_table(k6: np.ndarray, spacing=(1.0, 1.0, 1.0)) -> np.ndarray:
+    """Per-phase input features: the tensor entries, mapped to a grid whose
+    voxels are spacing (x, y, z) times the medium's, over the largest
+    eigenvalue (mrtlbm_nn_feature_table)."""
+    k = np.ascontiguousarray(k6, dtype=np.float64)
+    sp = np.ascontiguousarray(spacing, dtype=np.float64)
+    out = np.empty((k.shape[0], 6), np.float32)
+    dp, fp = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float)
+    check(load().mrtlbm_nn_feature_table(k.ctypes.data_as(dp), k.shape[0], sp.ctypes.data_as(dp),
+                                         out.ctypes.data_as(fp)))
+    return out
 
 
 class Net:
@@ -309,11 +315,11 @@ def linear_start(shape, device, dtype=torch.float32):
 
 
 def solve_fields(media, tol=1e-4, check_every=1000, max_steps=5_000_000, start="linear", net=None, batch=True,
-                 precision="f32"):
+                 precision="f32", storage="populations", keep_fields=True):
     """Steady x-gradient fields of canonical media (periodic sides).
 
     start: "zero", "linear" or "learned" (needs net).  Returns (temperature
-    tensors, results, setup seconds, number of rejected predictions)."""
+    tensors or None, results, setup seconds, number of rejected predictions)."""
     from .solver import Medium, batch_solve
 
     cells = []
@@ -321,6 +327,7 @@ def solve_fields(media, tol=1e-4, check_every=1000, max_steps=5_000_000, start="
     fallbacks = 0
     for m in media:
         g = Medium(m.phase, m.k, precision=precision)
+        g.set_storage(storage)
         g.set_bc(0, 1.0, 0.0, ("periodic",) * 3)
         if start == "zero":
             g.init()
@@ -340,38 +347,27 @@ def solve_fields(media, tol=1e-4, check_every=1000, max_steps=5_000_000, start="
         res, _ = batch_solve(cells, tol=tol, kind="keff", max_steps=max_steps, check_every=check_every)
     else:
         res = [g.solve(tol, "keff", max_steps, check_every=check_every) for g in cells]
-    temps = [g.temperature() for g in cells]
+    temps = [g.temperature() for g in cells] if keep_fields else None
     return temps, res, setup, fallbacks
 
 
 def predict_start(net: Net, m, g) -> tuple[torch.Tensor, int]:
     """Network start field for medium m on solver medium g (x gradient).
-    Cells larger than the network's grid are averaged down by 2x steps, the
-    prediction is interpolated back.  Returns (T0, number of rejected values)."""
+    The cell is resampled to the network's n^3 grid (a box average of the
+    per-voxel features, with the tensors mapped to the new voxel spacing),
+    and the prediction is interpolated back to the cell's own grid.
+    Returns (T0, number of rejected values)."""
     L = net.L
     n = net.n
     nz, ny, nx = m.phase.shape
-    f = nx // n
-    assert nx == ny == nz == n * f and f in (1, 2, 4), "cubic cells of n * {1, 2, 4} voxels"
     s = net.stream
-    feat = torch.from_numpy(feature_table(m.k)).to(net.dev)
-    phase = g.phase
-    if f == 1:
-        net.set_input(0, phase, feat)
-    else:
-        big = torch.empty((nx ** 3, 8), dtype=torch.bfloat16, device=net.dev)
-        check(L.mrtlbm_nn_features(_p(phase), nx, nx, nx, _p(feat), _p(big), s))
-        cur, size = big, nx
-        while size > n:
-            nxt = torch.empty(((size // 2) ** 3, 8), dtype=torch.bfloat16, device=net.dev) if size // 2 > n \
-                else net.act["x"][: n ** 3]
-            check(L.mrtlbm_nn_pool2(1, _p(cur), 1, size, size, size, 8, _p(nxt), s))
-            cur, size = nxt, size // 2
+    feat = torch.from_numpy(feature_table(m.k, (nx / n, ny / n, nz / n))).to(net.dev)
+    check(L.mrtlbm_nn_features_resampled(_p(g.phase), nz, ny, nx, _p(feat), n, n, n, _p(net.act["x"]), s))
     net.forward()
-    T0 = torch.empty((nx, nx, nx), dtype=torch.float32, device=net.dev)
+    T0 = torch.empty((nz, ny, nx), dtype=torch.float32, device=net.dev)
     bad_scratch = torch.empty(2048, dtype=torch.int32, device=net.dev)
     bad = ctypes.c_longlong()
-    check(L.mrtlbm_nn_to_temperature(_p(net.out), 16, n, n, n, f, SCALE, MARGIN, _p(T0), _p(bad_scratch),
+    check(L.mrtlbm_nn_to_temperature(_p(net.out), 16, n, n, n, nz, ny, nx, SCALE, MARGIN, _p(T0), _p(bad_scratch),
                                      ctypes.byref(bad), s))
     return T0, bad.value
 

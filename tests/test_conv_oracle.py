@@ -100,6 +100,52 @@ def test_pool_and_upsample_adjoints():
     assert np.allclose(C.pool2(C.up2(y)), y)
 
 
+def test_box_resample_pins():
+    from scipy import ndimage
+
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((6, 8, 12, 3))
+    # equal sizes: identity; halving: the 2x2x2 mean (numpy reshape)
+    assert np.array_equal(C.box_resample(x, (6, 8, 12)), x)
+    half = x.reshape(3, 2, 4, 2, 6, 2, 3).mean(axis=(1, 3, 5))
+    assert np.allclose(C.box_resample(x, (3, 4, 6)), half, rtol=0, atol=1e-14)
+    # ratio 1.5 along x (12 -> 8): fine centres 0..11 fall in coarse cells
+    # 0,0,1,1,2,...; cell c takes fine voxels {floor(1.5c + 0.25) .. }: brute
+    # force from the centre positions in floating point
+    y = C.box_resample(x, (6, 8, 8))
+    for cx in range(8):
+        members = [i for i in range(12) if int(np.floor((i + 0.5) / 12 * 8)) == cx]
+        assert np.allclose(y[:, :, cx], x[:, :, members].mean(axis=2), atol=1e-14)
+    # uniform refinement (6 -> 12 along z): every coarse voxel has no member
+    # and takes the fine voxel under its centre = nearest-neighbour zoom
+    z = C.box_resample(x, (12, 8, 12))
+    assert np.array_equal(z, ndimage.zoom(x, (2, 1, 1, 1), order=0, mode="grid-constant", grid_mode=True))
+    # the mean is preserved whenever every coarse voxel has equally many members
+    assert np.isclose(C.box_resample(x, (3, 2, 4)).mean(), x.mean())
+
+
+def test_interp_to_fine_pins():
+    from scipy import ndimage
+
+    rng = np.random.default_rng(6)
+    p = rng.standard_normal((4, 6, 8))
+    assert np.allclose(C.interp_to_fine(p, p.shape), p, atol=1e-15)
+    # library: pad y, z periodically and x by edge values, then linear
+    # map_coordinates at the fine centres' coarse coordinates
+    shape = (6, 9, 13)
+    padded = np.pad(np.pad(p, ((1, 1), (1, 1), (0, 0)), mode="wrap"), ((0, 0), (0, 0), (1, 1)), mode="edge")
+    zz, yy, xx = np.meshgrid(*[(np.arange(n) + 0.5) * nc / n - 0.5 for n, nc in zip(shape, p.shape)], indexing="ij")
+    xx = np.clip(xx, 0, p.shape[2] - 1)
+    ref = ndimage.map_coordinates(padded, [zz + 1, yy + 1, xx + 1], order=1, mode="nearest")
+    assert np.allclose(C.interp_to_fine(p, shape), ref, atol=1e-13)
+    # a profile linear in x is reproduced between the first and last centre
+    lin = np.broadcast_to(np.arange(8, dtype=float) * 0.3 - 1.0, (4, 6, 8))
+    f = C.interp_to_fine(lin, (4, 6, 32))
+    xs = (np.arange(32) + 0.5) * 8 / 32 - 0.5
+    inside = (xs >= 0) & (xs <= 7)
+    assert np.allclose(f[..., inside], xs[inside] * 0.3 - 1.0, atol=1e-14)
+
+
 def test_mse_gradient():
     rng = np.random.default_rng(5)
     p = rng.standard_normal(20)

@@ -291,3 +291,79 @@ def test_whole_network_forward_and_gradients(env):
     # keep cosine >= 0.99 (every single kernel meets 0.999 on its own)
     for name, (cos, rl2, rlb) in report.items():
         assert cos > 0.99 and rl2 < 0.2, (name, cos, rl2)
+
+
+@pytest.mark.parametrize("coarse", [(10, 12, 20), (5, 6, 10), (8, 8, 8), (16, 16, 16), (4, 12, 7)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_resampled_features(env, coarse):
+    L, torch = env
+    rng = np.random.default_rng(21)
+    D, H, W = 10, 12, 20
+    phase = rng.integers(0, 5, (D, H, W)).astype(np.uint8)
+    feat = rng.uniform(-1, 1, (5, 6)).astype(np.float32)
+    out = torch.empty((int(np.prod(coarse)), 8), dtype=torch.bfloat16, device="cuda")
+    ph, fd = torch.from_numpy(phase).cuda(), torch.from_numpy(feat).cuda()
+    assert L.mrtlbm_nn_features_resampled(P(ph), D, H, W, P(fd), *coarse, P(out), None) == 0
+    got = out.float().cpu().numpy().astype(np.float64).reshape(coarse + (8,))
+    ref = C.box_resample(feat.astype(np.float64)[phase], coarse)
+    # one BF16 rounding of an FP32 mean
+    assert np.all(np.abs(got[..., :6] - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-6)
+    xc = (np.arange(coarse[2]) + 0.5) / coarse[2] - 0.5
+    assert np.allclose(got[..., 6], np.broadcast_to(xc, coarse), atol=2.0 ** -9)
+    assert not got[..., 7].any()
+
+
+@pytest.mark.parametrize("grids", [((8, 8, 8), (8, 8, 8)), ((4, 6, 8), (6, 9, 13)), ((8, 8, 8), (12, 16, 24)),
+                                   ((8, 8, 8), (4, 8, 6))], ids=lambda g: "x".join(map(str, g[0] + g[1])))
+def test_start_field_interpolation(env, grids):
+    L, torch = env
+    (Dc, Hc, Wc), fine = grids
+    rng = np.random.default_rng(22)
+    scale, margin = 10.0, 0.05
+    pred = rng.uniform(-0.2, 0.2, (Dc, Hc, Wc, 16)).astype(np.float32)
+    pred[Dc // 2, Hc // 3, Wc // 2, 0] = 30.0  # pushes part of the field out of range
+    T = torch.empty(fine, dtype=torch.float32, device="cuda")
+    scratch = torch.empty(2048, dtype=torch.int32, device="cuda")
+    bad = ctypes.c_longlong()
+    pd = torch.from_numpy(pred).cuda()
+    assert L.mrtlbm_nn_to_temperature(P(pd), 16, Dc, Hc, Wc, *fine, scale, margin, P(T), P(scratch),
+                                      ctypes.byref(bad), None) == 0
+    W = fine[2]
+    tlin = 1.0 - (np.arange(W) + 0.5) / W
+    ref = tlin + C.interp_to_fine(pred[..., 0].astype(np.float64), fine) / scale
+    assert np.abs(T.cpu().numpy() - ref).max() < 1e-5
+    out = (ref < -margin) | (ref > 1 + margin)
+    edge = np.minimum(np.abs(ref + margin), np.abs(ref - 1 - margin))
+    assert edge.min() > 1e-4  # no value sits within rounding of a threshold
+    assert bad.value == int(out.sum()) and bad.value > 0
+
+
+def test_feature_table_spacing(env):
+    L, torch = env
+    rng = np.random.default_rng(23)
+    A = rng.standard_normal((4, 3, 3))
+    K = A @ A.transpose(0, 2, 1) + 0.3 * np.eye(3)
+    k6 = np.stack([K[:, 0, 0], K[:, 1, 1], K[:, 2, 2], K[:, 0, 1], K[:, 0, 2], K[:, 1, 2]], axis=1)
+
+    def table(k, sp):
+        k = np.ascontiguousarray(k, np.float64)
+        sp = np.ascontiguousarray(sp, np.float64)
+        out = np.empty((k.shape[0], 6), np.float32)
+        dp = ctypes.POINTER(ctypes.c_double)
+        st = L.mrtlbm_nn_feature_table(k.ctypes.data_as(dp), k.shape[0], sp.ctypes.data_as(dp),
+                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+        return st, out
+
+    sp = (1.5, 1.0, 2.0)
+    st, got = table(k6, sp)
+    assert st == 0
+    S = np.diag(1.0 / np.asarray(sp))
+    Kt = S @ K @ S  # K'_ab = K_ab / (s_a s_b)
+    ref = np.stack([Kt[:, 0, 0], Kt[:, 1, 1], Kt[:, 2, 2], Kt[:, 0, 1], Kt[:, 0, 2], Kt[:, 1, 2]], axis=1)
+    ref /= np.linalg.eigvalsh(Kt).max()
+    assert np.allclose(got, ref, rtol=1e-6, atol=1e-7)
+    # a uniform power-of-two spacing changes nothing, bit for bit
+    assert np.array_equal(table(k6, (1, 1, 1))[1], table(k6, (2, 2, 2))[1])
+    bad = k6.copy()
+    bad[1, 3] = 10.0 * np.sqrt(bad[1, 0] * bad[1, 1])
+    assert table(bad, sp)[0] == -2  # E_TENSOR

@@ -139,7 +139,10 @@ def test_launch_shapes_bitwise_identical(Medium, launch):
     import torch
 
     assert torch.equal(ref.state_get(), g.state_get())
-    assert ref.keff() == g.keff() or abs(ref.keff()["keff_hot"] - g.keff()["keff_hot"]) < 1e-15
+    # the FP64 observables are sums in a launch-shape-dependent order
+    ka, kb = ref.keff(), g.keff()
+    for key in ("keff_hot", "keff_cold", "keff_vol", "resid"):
+        assert abs(ka[key] - kb[key]) <= 1e-13 * max(1.0, abs(ka[key])), key
 
 
 def test_checkpoint_resume_bitwise(Medium):
