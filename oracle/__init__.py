@@ -61,6 +61,8 @@ def lib():
         L.oracle_set_threads.argtypes = [P, I]
         L.oracle_set_bc.restype = I
         L.oracle_set_bc.argtypes = [P, I, D, D, ctypes.POINTER(ctypes.c_int)]
+        L.oracle_set_side_flux.restype = I
+        L.oracle_set_side_flux.argtypes = [P, I, D, D]
         L.oracle_init.argtypes = [P, dp]
         L.oracle_collide_node.argtypes = [P, I, dp, dp]
         L.oracle_step.argtypes = [P, LL]
@@ -134,6 +136,12 @@ class Oracle:
         if lib().oracle_set_bc(self._h, int(grad_axis), float(t_hot), float(t_cold), arr):
             raise ValueError("bad boundary specification")
         self.grad_axis, self.t_hot, self.t_cold = int(grad_axis), float(t_hot), float(t_cold)
+
+    def set_side_flux(self, axis: int, q_lo: float, q_hi: float):
+        """Heat flux into the cell through the two faces of an adiabatic axis
+        (Eq. 24; physical units of k times temperature per voxel)."""
+        if lib().oracle_set_side_flux(self._h, int(axis), float(q_lo), float(q_hi)):
+            raise ValueError("side flux needs an adiabatic axis")
 
     def init(self, T0=None):
         if T0 is None:

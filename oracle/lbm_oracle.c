@@ -18,7 +18,7 @@
  *   - tau_ij = delta_ij / 2 + D_ij / epsilon in lattice units (Eq. 13),
  *   - collision f_hat = f - M^-1 S M (f - f_eq)  (Eqs. 5, 8),
  *   - push streaming (Eq. 21) -- unchanged across internal interfaces,
- *     half-way Dirichlet (Eq. 23), adiabatic Neumann with zero flux (Eq. 24)
+ *     half-way Dirichlet (Eq. 23), Neumann with a given (default zero) flux (Eq. 24)
  *     and periodic (Eq. 25) walls,
  *   - T = sum f (Eq. 14), grad T from the 3x3 system of Eq. 15, heat flux
  *     q = -D grad T (Eq. 16 with the sign of Fourier's law, Eq. 27), and the
@@ -65,6 +65,7 @@ typedef struct {
     int grad_axis;
     double t_hot, t_cold;
     int side[3];
+    double qside[3][2];       /* imposed inward heat flux on the two faces of an adiabatic axis (physical) */
     double *f, *fpost, *fnew; /* [Q][n] */
     long long steps;
     double phi_hot, phi_cold; /* wall link fluxes of the last streaming */
@@ -268,6 +269,7 @@ void oracle_set_threads(oracle_ctx *c, int n) { c->nthreads = n; }
 int oracle_set_bc(oracle_ctx *c, int grad_axis, double t_hot, double t_cold, const int *side) {
     if (grad_axis < 0 || grad_axis > 2) return -1;
     c->grad_axis = grad_axis; c->t_hot = t_hot; c->t_cold = t_cold;
+    memset(c->qside, 0, sizeof(c->qside));
     for (int a = 0; a < 3; a++) {
         if (a == grad_axis) c->side[a] = SIDE_DIRICHLET;
         else {
@@ -275,6 +277,17 @@ int oracle_set_bc(oracle_ctx *c, int grad_axis, double t_hot, double t_cold, con
             c->side[a] = side[a];
         }
     }
+    return 0;
+}
+
+/* Neumann faces with a non-zero flux (Eq. 24): q_lo / q_hi = heat flux into
+ * the cell through the index-0 / last face of an adiabatic axis, in the
+ * units of k times temperature per voxel; the lattice flux phi_n per link
+ * and step is s q.  Cleared by oracle_set_bc. */
+int oracle_set_side_flux(oracle_ctx *c, int axis, double q_lo, double q_hi) {
+    if (axis < 0 || axis > 2 || c->side[axis] != SIDE_ADIABATIC) return -1;
+    c->qside[axis][0] = q_lo;
+    c->qside[axis][1] = q_hi;
     return 0;
 }
 
@@ -335,7 +348,9 @@ static void one_step(oracle_ctx *c) {
                         long long didx = ((long long)dst[2] * ny + dst[1]) * nx + dst[0];
                         c->fnew[i * n + didx] = fo; /* Eq. 21 */
                     } else if (c->side[a] == SIDE_ADIABATIC) {
-                        c->fnew[OPP[i] * n + idx] = fo; /* Eq. 24, phi_n = 0 */
+                        /* Eq. 24 with delta t / delta x = 1: the reflected population
+                         * plus the lattice flux entering through this face */
+                        c->fnew[OPP[i] * n + idx] = fo + c->s * c->qside[a][dir < 0 ? 0 : 1];
                     } else {
                         double tw = dir < 0 ? c->t_hot : c->t_cold;
                         c->fnew[OPP[i] * n + idx] = -fo + EPS * tw; /* Eq. 23 */
@@ -442,7 +457,13 @@ int oracle_solve(oracle_ctx *c, double tol, int kind, long long max_steps, int c
             double ng = dims[c->grad_axis], area = (double)c->n / ng, dT = c->t_hot - c->t_cold;
             double kh = ng * c->phi_hot / (dT * area * c->s), kc = ng * c->phi_cold / (dT * area * c->s);
             double km = 0.5 * (kh + kc);
-            int gap_ok = fabs(kh - kc) < tol * fabs(km);
+            /* steady state: what enters through the hot wall and the
+             * Neumann faces leaves through the cold wall */
+            double side_in = 0.0;
+            for (int a = 0; a < 3; a++)
+                side_in += c->s * (c->qside[a][0] + c->qside[a][1]) * ((double)c->n / dims[a]);
+            double ks = ng * side_in / (dT * area * c->s);
+            int gap_ok = fabs(kh - kc + ks) < tol * fabs(km);
             int chg_ok = kprev == kprev && fabs(km - kprev) < 0.1 * tol * fabs(km);
             kprev = km;
             if (gap_ok && chg_ok) { conv = 1; break; }

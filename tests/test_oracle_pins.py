@@ -156,9 +156,83 @@ def test_energy_identity_per_step():
     assert math.isclose(lf["phi_cold"], phi_cold, rel_tol=1e-12)
 
 
+def test_energy_identity_with_side_flux():
+    # Eq. 24 with phi_n != 0: each Neumann link adds s q per step
+    m = w.random_medium(23, 6, 5, 4, nphase=3)
+    o = make(m, grad=2, sides=(ADIABATIC, ADIABATIC, 0), t_hot=0.6, t_cold=-0.2)
+    qs = {0: (0.3, -0.7), 1: (-0.2, 0.45)}
+    for a, (lo, hi) in qs.items():
+        o.set_side_flux(a, lo, hi)
+    rng = np.random.default_rng(3)
+    f = rng.uniform(0, 0.2, (7,) + m.phase.shape)
+    o.set_f(f)
+    fh = _post_collision(o, m, f)
+    before = f.sum()
+    o.step(1)
+    after = o.get_f().sum()
+    phi_hot = (EPS * 0.6 - 2 * fh[6][0, :, :]).sum()
+    phi_cold = (2 * fh[5][-1, :, :] - EPS * (-0.2)).sum()
+    nz, ny, nx = m.phase.shape
+    side = o.scale * ((qs[0][0] + qs[0][1]) * ny * nz + (qs[1][0] + qs[1][1]) * nx * nz)
+    assert math.isclose(after - before, phi_hot - phi_cold + side, rel_tol=1e-12, abs_tol=1e-13)
+    # the reflected link itself: population 1 re-enters at x = 0 as f_hat_2 + s q_lo
+    assert np.allclose(o.get_f()[1][:, :, 0], fh[2][:, :, 0] + o.scale * qs[0][0], atol=1e-14)
+    assert np.allclose(o.get_f()[4][:, -1, :], fh[3][:, -1, :] + o.scale * qs[1][1], atol=1e-14)
+
+
 # ---------------------------------------------------------------------------
 # closed-form steady states
 # ---------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("tau_rest", [(1, 1, 1, 1), (1, 0.7, 1.6, 1.2)])
+def test_side_flux_of_the_linear_solution_makes_it_exact(tau_rest):
+    """A homogeneous anisotropic cell with a z gradient: with periodic sides
+    the steady field is T_lin(z) and the flux q = -K grad T has side
+    components q_x = K_xz dT/L, q_y = K_yz dT/L.  Imposing exactly those
+    fluxes on Neumann x and y faces (in through the low face, out through the
+    high one) keeps T_lin(z) exact, so k = K_zz; zero flux (adiabatic) does
+    not.  Holds for any tau_4..6."""
+    rng = np.random.default_rng(33)
+    K = w.random_spd(rng, 0.3, 1.5)
+    K[0, 2] = K[2, 0] = 0.3
+    K[1, 2] = K[2, 1] = -0.25
+    assert np.all(np.linalg.eigvalsh(K) > 0)
+    nx, ny, nz = 5, 4, 9
+    m = w.Medium(np.zeros((nz, ny, nx), np.uint8), w.sym6(K)[None, :])
+    dT = 1.0
+    o = make(m, grad=2, sides=(ADIABATIC, ADIABATIC, 0), tau_rest=np.array(tau_rest, float))
+    qx, qy = K[0, 2] * dT / nz, K[1, 2] * dT / nz
+    o.set_side_flux(0, qx, -qx)
+    o.set_side_flux(1, qy, -qy)
+    r = o.solve(1e-15, TOL_MAXDT, 2_000_000)
+    tlin = 1.0 - (np.arange(nz) + 0.5) / nz
+    assert np.allclose(o.temperature(), tlin[:, None, None], rtol=0, atol=1e-11)
+    assert math.isclose(r["keff_hot"], K[2, 2], rel_tol=1e-9)
+    assert math.isclose(r["keff_cold"], K[2, 2], rel_tol=1e-9)
+    # the energy-balance stop rule sees the side inflow (here zero net)
+    o2 = make(m, grad=2, sides=(ADIABATIC, ADIABATIC, 0), tau_rest=np.array(tau_rest, float))
+    o2.set_side_flux(0, qx, -qx)
+    o2.set_side_flux(1, qy, -qy)
+    assert o2.solve(1e-9, TOL_KEFF, 2_000_000, check_every=20)["converged"]
+    a = make(m, grad=2, sides=(ADIABATIC, ADIABATIC, 0), tau_rest=np.array(tau_rest, float))
+    ra = a.solve(1e-15, TOL_MAXDT, 2_000_000)
+    assert ra["keff_hot"] < K[2, 2] * (1 - 1e-3)
+
+
+def test_side_inflow_balances_at_steady_state():
+    # net heat put in through the sides leaves through the walls:
+    # Phi_cold - Phi_hot = s * sum of q * face area
+    m = w.random_medium(24, 5, 6, 4, nphase=2)
+    o = make(m, grad=0, sides=(0, ADIABATIC, ADIABATIC))
+    o.set_side_flux(1, 0.05, 0.02)
+    o.set_side_flux(2, -0.01, 0.04)
+    o.solve(1e-15, TOL_MAXDT, 2_000_000)
+    o.step(1)
+    lf = o.last_fluxes()
+    nz, ny, nx = m.phase.shape
+    side = o.scale * ((0.05 + 0.02) * nx * nz + (-0.01 + 0.04) * nx * ny)
+    assert math.isclose(lf["phi_cold"] - lf["phi_hot"], side, rel_tol=1e-9)
 
 
 def test_c1_layered_series_mean():
