@@ -50,10 +50,15 @@ def bytes_per_update(prec: str, storage: str) -> float:
     """Algorithmic HBM bytes of one lattice update: the state read and
     written once (7 populations or 4 moments) plus the phase byte."""
     return 2.0 * STORAGE_VALUES[storage] * (8 if prec == "f64" else 4) + 1.0
-# HBM bytes per k_step launch on braid256_f32 from rocprofv3 --pmc FETCH_SIZE /
-# WRITE_SIZE (KiB per dispatch), each scaled by the counter's reading for a
-# plain copy of known size; None once the kernel changes.
-MEASURED_TRAFFIC = {}
+# HBM bytes per k_step launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
+# (KiB per dispatch, mean over 109 dispatches), each scaled by the counter's
+# reading for a plain 1 GiB copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000);
+# keyed by workload, storage and launch shape (vec, bx, by, nt, map).  Drop an
+# entry whenever its kernel changes.
+MEASURED_TRAFFIC = {
+    ("braid256_f32", "moments", (4, 64, 4, 2, 1)): 563_282_555,
+    ("braid256_f32", "populations", (4, 64, 1, 3, 1)): 956_361_450,
+}
 
 
 def parse():
@@ -177,6 +182,7 @@ def mode_throughput(args):
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
+            "traffic_vs_algorithmic": None if traffic is None else round(traffic / (bpl * nodes), 4),
             "kernel": "k_step",
             "kernel_us": round(kern_us, 3),
             "bytes_per_update": bpl,
@@ -208,15 +214,20 @@ def mode_copy(args):
             "GB_s": round(8 * n / dt / 1e9, 1)}
 
 
-def _solve(m, prec, axis, sides, tol, args, T0=None, flux=False, start="zero", net=None):
+def _solve(m, prec, axis, sides, tol, args, T0=None, flux=False, start="zero", net=None, canonical=False):
+    """One steady solve along axis.  The learned start (and canonical=True)
+    solves the medium permuted so that the gradient runs along x; a given
+    start field T0 must then be in that frame too."""
     import torch
 
     from paper_1503_08718_amd import warmstart
 
     mm = m
-    if start == "learned":
+    swap = (0, 1, 2)
+    if start == "learned" or canonical:
         # the network works on media whose gradient runs along x
-        mm = m if axis == 0 else m.permuted({1: (1, 0, 2), 2: (2, 1, 0)}[axis])
+        swap = {0: (0, 1, 2), 1: (1, 0, 2), 2: (2, 1, 0)}[axis]
+        mm = m if axis == 0 else m.permuted(swap)
         axis = 0
     g = _medium(mm, prec, args)
     g.set_bc(axis, 1.0, 0.0, (sides,) * 3)
@@ -240,13 +251,15 @@ def _solve(m, prec, axis, sides, tol, args, T0=None, flux=False, start="zero", n
     r = g.solve(tol, "keff", args.max_steps, check_every=1000)
     torch.cuda.synchronize()
     r["seconds"] = round(time.perf_counter() - t0, 3)
+    # flux column back in the cell's own axes (the exchange is its own inverse)
+    r["keff_col"] = [r["keff_col"][swap[a]] for a in range(3)]
     return g, r
 
 
 def mode_solve(args):
-    """Steady solves of one braided cell.  Default: FP32 from a zero start,
-    then an FP64 reference started from the FP32 field; with --precision the
-    single requested solve (from --start) is run instead."""
+    """Steady solves of one braided cell.  Default: FP32 from --start, then an
+    FP64 reference (tolerance --ref-tol) started from the FP32 field; with
+    --precision the single requested solve (from --start) is run instead."""
     import workloads
 
     m = workloads.braid(args.n, args.n, args.n, args.gamma, args.vf)
@@ -264,11 +277,12 @@ def mode_solve(args):
             rec = {"axis": "xyz"[axis], "precision": args.precision, "start": args.start,
                    "result": {k: r[k] for k in keys}, "MLUPS": round(m.phase.size * r["steps"] / r["seconds"] / 1e6, 1)}
         else:
-            g32, r32 = _solve(m, "f32", axis, args.sides, args.tol, args)
-            rec = {"axis": "xyz"[axis], "f32": {k: r32[k] for k in keys}}
+            g32, r32 = _solve(m, "f32", axis, args.sides, args.tol, args, start=args.start, net=net)
+            rec = {"axis": "xyz"[axis], "start": args.start, "f32": {k: r32[k] for k in keys}}
             if not args.no_ref:
                 T = g32.temperature().double()
-                g64, r64 = _solve(m, "f64", axis, args.sides, args.ref_tol, args, T0=T, flux=True)
+                g64, r64 = _solve(m, "f64", axis, args.sides, args.ref_tol, args, T0=T, flux=True,
+                                  canonical=(args.start == "learned"))
                 rec["f64_ref"] = {k: r64[k] for k in keys}
                 rec["f32_rel_err"] = abs(r32["keff"] - r64["keff"]) / abs(r64["keff"])
                 rec["f32_rel_err_vol"] = abs(r32["keff_vol"] - r64["keff_vol"]) / abs(r64["keff_vol"])

@@ -51,8 +51,11 @@ typedef enum { MRTLBM_F32 = 0, MRTLBM_F64 = 1 } mrtlbm_precision;
 typedef enum { MRTLBM_PERIODIC = 0, MRTLBM_ADIABATIC = 1 } mrtlbm_side;
 typedef enum {
     MRTLBM_TOL_MAXDT = 0, /* stop when max |T(t) - T(t-1)| at a check < tol                        */
-    MRTLBM_TOL_KEFF = 1   /* stop when |k_hot - k_cold + k_leak| / k < tol and the last change of k
-                             between checks, with its geometric tail, is < tol/4 */
+    MRTLBM_TOL_KEFF = 1   /* stop after two checks in a row at which: the energy balance
+                             |k_hot - k_cold + k_side + k_leak| / k < tol; the volume-mean flux
+                             agrees, |k_vol - k| / k < tol (skipped when side fluxes are set);
+                             and the last change of k between checks, with its geometric tail,
+                             is < tol/4 */
 } mrtlbm_tol_kind;
 
 typedef struct mrtlbm_medium mrtlbm_medium;
@@ -72,7 +75,14 @@ typedef struct mrtlbm_medium mrtlbm_medium;
  *       added to the stored state (summed exactly in FP64); at steady state
  *       keff_hot - keff_cold + keff_leak = 0, and the MRTLBM_TOL_KEFF rule
  *       tests |keff_hot - keff_cold + keff_leak| / keff (the stored energy's
- *       rate of change), which equals the wall-flux gap in exact arithmetic.
+ *       rate of change), which equals the wall-flux gap in exact arithmetic,
+ *       together with |keff_vol - keff| (transients that move heat inside
+ *       the cell without changing its energy) and the change of keff;
+ *   keff_side: the heat imposed through Neumann faces in the same units
+ *       (0 unless mrtlbm_set_side_flux was called); at steady state
+ *       keff_hot - keff_cold + keff_side + keff_leak = 0, and the rule
+ *       includes it.  With side inflow the two wall fluxes differ and keff is
+ *       only their mean, not a conductivity.
  */
 typedef struct {
     double keff, keff_hot, keff_cold, keff_vol;
@@ -80,6 +90,7 @@ typedef struct {
     double resid;
     double temp_mean;
     double keff_leak;
+    double keff_side; /* heat imposed through Neumann faces (mrtlbm_set_side_flux), N_g sum(q A_f) / (dT A) */
     long long steps;  /* steps taken by the medium when the values were taken */
     int converged;
     int nonfinite;    /* nodes whose T(t+1) is not finite */
@@ -127,6 +138,22 @@ mrtlbm_status mrtlbm_create(int nx, int ny, int nz, const unsigned char *phase_d
  * state: call mrtlbm_init afterwards. */
 mrtlbm_status mrtlbm_set_bc(mrtlbm_medium *m, int grad_axis, double t_hot, double t_cold,
                             const int side[3]);
+
+/* Neumann faces with a given heat flux (Eq. 24): q_lo and q_hi are the heat
+ * fluxes INTO the cell through the index-0 and the last face of `axis`, in
+ * the units of mrtlbm_flux (k times temperature per voxel); each wall link
+ * then re-enters with the reflected population plus s * q.  axis must be a
+ * side with MRTLBM_ADIABATIC faces (E_BC otherwise); mrtlbm_set_bc resets
+ * both to 0.  The state stays valid.  Errors: E_ARG (NULL, not finite), E_BC. */
+mrtlbm_status mrtlbm_set_side_flux(mrtlbm_medium *m, int axis, double q_lo, double q_hi);
+
+/* Relaxation times tau_4, tau_5, tau_6 of Eq. 12 (default 1, as the paper
+ * sets them), one set for all phases; each must exceed 1/2.  Values other
+ * than 1 need population storage (E_ARG under moment storage, and
+ * mrtlbm_set_storage(m, 1) then fails) and are not accepted by
+ * mrtlbm_batch_solve.  The step then relaxes all six non-conserved moments of
+ * Eq. 11 (7 populations per node).  The state stays valid. */
+mrtlbm_status mrtlbm_set_relaxation(mrtlbm_medium *m, double tau4, double tau5, double tau6);
 
 /* Relaxation scale: largest eigenvalue of tau - I/2 over all phases
  * (Eq. 13; the paper keeps tau_ii in (0.5, 2)).  0 < dmax <= 1.5.

@@ -34,6 +34,7 @@ class Result(ctypes.Structure):
         ("resid", ctypes.c_double),
         ("temp_mean", ctypes.c_double),
         ("keff_leak", ctypes.c_double),
+        ("keff_side", ctypes.c_double),
         ("steps", ctypes.c_longlong),
         ("converged", ctypes.c_int),
         ("nonfinite", ctypes.c_int),
@@ -42,7 +43,7 @@ class Result(ctypes.Structure):
     def to_dict(self) -> dict:
         return dict(keff=self.keff, keff_hot=self.keff_hot, keff_cold=self.keff_cold, keff_vol=self.keff_vol,
                     keff_col=list(self.keff_col), resid=self.resid, temp_mean=self.temp_mean,
-                    keff_leak=self.keff_leak, steps=self.steps,
+                    keff_leak=self.keff_leak, keff_side=self.keff_side, steps=self.steps,
                     converged=bool(self.converged), nonfinite=self.nonfinite)
 
 
@@ -103,6 +104,8 @@ def load():
         "mrtlbm_create": (I, [I, I, I, P, ctypes.POINTER(ctypes.c_double), I, I, P, SZ, P, PP]),
         "mrtlbm_set_bc": (I, [P, I, D, D, ctypes.POINTER(ctypes.c_int)]),
         "mrtlbm_set_scale": (I, [P, D]),
+        "mrtlbm_set_side_flux": (I, [P, I, D, D]),
+        "mrtlbm_set_relaxation": (I, [P, D, D, D]),
         "mrtlbm_init": (I, [P, P, I]),
         "mrtlbm_step": (I, [P, LL]),
         "mrtlbm_solve": (I, [P, D, I, LL, I, RP]),

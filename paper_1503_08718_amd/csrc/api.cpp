@@ -218,6 +218,11 @@ Cell<real> mrt::make_cell(const mrtlbm_medium *m, int cur) {
     }
     c.gaxis = m->gaxis;
     c.storage = m->storage;
+    c.relax = (m->tau_rest[0] != 1.0 || m->tau_rest[1] != 1.0 || m->tau_rest[2] != 1.0) ? 1 : 0;
+    for (int i = 0; i < 3; i++) c.srel[i] = (real)(1.0 / m->tau_rest[i]);
+    // Eq. 24 in lattice units: the inflow per link and step is s q
+    for (int a = 0; a < 3; a++)
+        for (int e = 0; e < 2; e++) c.phi[a][e] = (real)(m->s * m->qside[a][e]);
     return c;
 }
 template Cell<float> mrt::make_cell<float>(const mrtlbm_medium *, int);
@@ -366,7 +371,31 @@ extern "C" mrtlbm_status mrtlbm_set_bc(mrtlbm_medium *m, int grad_axis, double t
     m->t_hot = t_hot;
     m->t_cold = t_cold;
     for (int a = 0; a < 3; a++) m->side[a] = (a == grad_axis) ? MRTLBM_PERIODIC : side[a];
+    for (int a = 0; a < 3; a++) m->qside[a][0] = m->qside[a][1] = 0.0;
     m->initialised = false;
+    drop_graphs(m);
+    return MRTLBM_OK;
+}
+
+extern "C" mrtlbm_status mrtlbm_set_side_flux(mrtlbm_medium *m, int axis, double q_lo, double q_hi) {
+    if (!m) return fail(MRTLBM_E_ARG, "medium is NULL");
+    if (axis < 0 || axis > 2 || axis == m->gaxis) return fail(MRTLBM_E_BC, "side flux on axis %d", axis);
+    if (m->side[axis] != MRTLBM_ADIABATIC) return fail(MRTLBM_E_BC, "axis %d has no Neumann faces", axis);
+    if (!std::isfinite(q_lo) || !std::isfinite(q_hi)) return fail(MRTLBM_E_ARG, "side flux not finite");
+    m->qside[axis][0] = q_lo;
+    m->qside[axis][1] = q_hi;
+    drop_graphs(m);
+    return MRTLBM_OK;
+}
+
+extern "C" mrtlbm_status mrtlbm_set_relaxation(mrtlbm_medium *m, double tau4, double tau5, double tau6) {
+    if (!m) return fail(MRTLBM_E_ARG, "medium is NULL");
+    const double t[3] = {tau4, tau5, tau6};
+    for (int i = 0; i < 3; i++)
+        if (!(t[i] > 0.5) || !std::isfinite(t[i])) return fail(MRTLBM_E_ARG, "tau_%d = %g must exceed 1/2", i + 4, t[i]);
+    if (m->storage && (tau4 != 1.0 || tau5 != 1.0 || tau6 != 1.0))
+        return fail(MRTLBM_E_ARG, "moment storage holds only tau_4 = tau_5 = tau_6 = 1");
+    for (int i = 0; i < 3; i++) m->tau_rest[i] = t[i];
     drop_graphs(m);
     return MRTLBM_OK;
 }
@@ -524,6 +553,11 @@ void mrt::fill_result(const mrtlbm_medium *m, const double *f, mrtlbm_result *ou
     out->temp_mean = f[R_TSUM] / (double)m->N + 0.5 * (m->t_hot + m->t_cold);
     out->nonfinite = (int)f[R_NONFINITE];
     out->keff_leak = ng * f[R_LEAK] / (dT * area * s);
+    // heat imposed through Neumann faces, in the same units: s q per link,
+    // one link per node of the face
+    double side_in = 0.0;
+    for (int a = 0; a < 3; a++) side_in += (m->qside[a][0] + m->qside[a][1]) * ((double)m->N / ext[a]);
+    out->keff_side = ng * side_in / (dT * area);
     out->steps = m->steps;
     out->converged = 0;
 }
@@ -565,16 +599,31 @@ extern "C" mrtlbm_status mrtlbm_temperature(mrtlbm_medium *m, void *t_dev) {
 }
 
 // stop rule shared by the single and the batched driver
+bool mrt::has_side_flux(const mrtlbm_medium *m) {
+    for (int a = 0; a < 3; a++)
+        if (m->qside[a][0] != 0.0 || m->qside[a][1] != 0.0) return true;
+    return false;
+}
+
 int mrt::stop_rule(StopState &ss, const mrtlbm_result &r, double tol, mrtlbm_tol_kind kind) {
     if (r.nonfinite) return -1;
     if (ss.min_resid > 0 && r.resid > 1e3 * ss.min_resid && r.resid > 1e-6) return -2;
     if (ss.min_resid < 0 || r.resid < ss.min_resid) ss.min_resid = r.resid;
     if (kind == MRTLBM_TOL_MAXDT) return r.resid < tol ? 1 : 0;
-    // energy accumulation rate through the walls plus the exact rounding
-    // energy of the stored state: dE/dt of the stored field, relative to the
-    // through-flux (equal to the plain wall-flux gap in exact arithmetic)
+    // energy accumulation rate through the walls and the Neumann faces plus
+    // the exact rounding energy of the stored state: dE/dt of the stored
+    // field, relative to the through-flux (equal to the plain wall-flux gap
+    // in exact arithmetic without side inflow)
     const double km = r.keff, ak = std::fabs(km);
-    const bool gap_ok = std::fabs(r.keff_hot - r.keff_cold + r.keff_leak) < tol * ak;
+    const bool gap_ok = std::fabs(r.keff_hot - r.keff_cold + r.keff_side + r.keff_leak) < tol * ak;
+    // the volume mean of the node flux averages every plane's flux; at steady
+    // state it equals the wall mean.  A transient mode that leaves the stored
+    // energy unchanged (it moves heat from one part of the cell to another)
+    // has equal wall fluxes, so the balance above misses it, but its plane
+    // fluxes differ inside the cell and pull the volume mean away (with heat
+    // imposed through side faces the plane fluxes differ at steady state too,
+    // and this test is off)
+    const bool vol_ok = !ss.check_vol || std::fabs(r.keff_vol - km) < tol * ak;
     // remaining change of k: the last change d between checks, extended by
     // its geometric tail d r / (1 - r), r = |d| / |previous d| (the slowest
     // mode decays geometrically); from a zero start T rises monotonically and
@@ -594,13 +643,17 @@ int mrt::stop_rule(StopState &ss, const mrtlbm_result &r, double tol, mrtlbm_tol
     }
     ss.kprev = km;
     ss.have_prev = true;
-    return (gap_ok && chg_ok) ? 1 : 0;
+    // two checks in a row, so that a turning point of k(t) that happens to
+    // meet the balance does not end the run
+    ss.passes = (gap_ok && vol_ok && chg_ok) ? ss.passes + 1 : 0;
+    return ss.passes >= 2 ? 1 : 0;
 }
 
 template <typename real>
 static mrtlbm_status do_solve(mrtlbm_medium *m, double tol, mrtlbm_tol_kind kind, long long max_steps, int K,
                               mrtlbm_result *out) {
     StopState ss;
+    ss.check_vol = !has_side_flux(m);
     mrtlbm_result r{};
     fill_result(m, std::vector<double>(NRED, 0.0).data(), &r);
     while (m->steps < max_steps) {
@@ -656,6 +709,8 @@ extern "C" int mrtlbm_state_values(const mrtlbm_medium *m) { return !m ? 0 : (m-
 extern "C" mrtlbm_status mrtlbm_set_storage(mrtlbm_medium *m, int storage) {
     if (!m) return fail(MRTLBM_E_ARG, "medium is NULL");
     if (storage != 0 && storage != 1) return fail(MRTLBM_E_ARG, "storage must be 0 or 1");
+    if (storage == 1 && (m->tau_rest[0] != 1.0 || m->tau_rest[1] != 1.0 || m->tau_rest[2] != 1.0))
+        return fail(MRTLBM_E_ARG, "moment storage holds only tau_4 = tau_5 = tau_6 = 1");
     m->storage = storage;
     m->initialised = false;
     drop_graphs(m);

@@ -132,6 +132,7 @@ mrtlbm_status run(BatchRun &B, double tol, mrtlbm_tol_kind kind, long long max_s
     mrtlbm_status st = upload_cells<real>(B);
     if (st != MRTLBM_OK) return st;
     std::vector<StopState> ss(B.n);
+    for (int i = 0; i < B.n; i++) ss[i].check_vol = !has_side_flux(B.cells[i]);
     std::vector<int> state(B.n, 0);  // 0 active, 1 converged, 2 out of steps, -1 non-finite, -2 diverged
     for (int i = 0; i < B.n; i++) {
         std::vector<double> zero(NRED, 0.0);
@@ -201,6 +202,8 @@ extern "C" mrtlbm_status mrtlbm_batch_solve(mrtlbm_medium *const *cells, int n, 
         if (!m->initialised) return fail(MRTLBM_E_ARG, "cell %d is not initialised", i);
         if (m->prec != m0->prec) return fail(MRTLBM_E_ARG, "cells mix precisions");
         if (m->storage != m0->storage) return fail(MRTLBM_E_ARG, "cells mix state storages");
+        if (m->tau_rest[0] != 1.0 || m->tau_rest[1] != 1.0 || m->tau_rest[2] != 1.0)
+            return fail(MRTLBM_E_ARG, "batched solves need tau_4 = tau_5 = tau_6 = 1 (cell %d)", i);
         if (m->stream != m0->stream || m->device != m0->device) return fail(MRTLBM_E_ARG, "cells mix streams/devices");
         while (m->nx % vec) vec >>= 1;
         max_nphase = std::max(max_nphase, m->nphase);

@@ -145,29 +145,32 @@ __device__ __forceinline__ void pull_dist(const Cell<real> &c, int xv, int y, in
     real rawHotX = 0, rawColdX = 0;
     if (x0 == 0) {
         if (c.per[0]) left = xl.haveL ? gotL : s[N + base + nx - 1];
-        else { rawHotX = a2.v[0]; left = c.sgn[0] * a2.v[0]; }
+        else { rawHotX = a2.v[0]; left = c.sgn[0] * a2.v[0] + c.phi[0][0]; }
     } else {
         left = xl.haveL ? gotL : s[N + base - 1];
     }
     if (x0 + VEC == nx) {
         if (c.per[0]) right = xl.haveR ? gotR : s[2 * N + base - x0];
-        else { rawColdX = a1.v[VEC - 1]; right = c.sgn[0] * a1.v[VEC - 1]; }
+        else { rawColdX = a1.v[VEC - 1]; right = c.sgn[0] * a1.v[VEC - 1] + c.phi[0][1]; }
     } else {
         right = xl.haveR ? gotR : s[2 * N + base + VEC];
     }
-    const real sy3 = (ylo && !c.per[1]) ? c.sgn[1] : real(1);
-    const real sy4 = (yhi && !c.per[1]) ? c.sgn[1] : real(1);
-    const real sz5 = (zlo && !c.per[2]) ? c.sgn[2] : real(1);
-    const real sz6 = (zhi && !c.per[2]) ? c.sgn[2] : real(1);
+    // wall links: reflection sign and the imposed inflow (Eq. 24; zero on
+    // Dirichlet and zero-flux faces)
+    const bool wy3 = ylo && !c.per[1], wy4 = yhi && !c.per[1], wz5 = zlo && !c.per[2], wz6 = zhi && !c.per[2];
+    const real sy3 = wy3 ? c.sgn[1] : real(1), py3 = wy3 ? c.phi[1][0] : real(0);
+    const real sy4 = wy4 ? c.sgn[1] : real(1), py4 = wy4 ? c.phi[1][1] : real(0);
+    const real sz5 = wz5 ? c.sgn[2] : real(1), pz5 = wz5 ? c.phi[2][0] : real(0);
+    const real sz6 = wz6 ? c.sgn[2] : real(1), pz6 = wz6 ? c.phi[2][1] : real(0);
 #pragma unroll
     for (int v = 0; v < VEC; v++) {
         P.f0[v] = c0.v[v];
         P.r[0][v] = (v == 0 ? left : a1.v[v - 1]);
         P.r[1][v] = (v == VEC - 1 ? right : a2.v[v + 1]);
-        P.r[2][v] = sy3 * b3.v[v];
-        P.r[3][v] = sy4 * b4.v[v];
-        P.r[4][v] = sz5 * b5.v[v];
-        P.r[5][v] = sz6 * b6.v[v];
+        P.r[2][v] = fma(sy3, b3.v[v], py3);
+        P.r[3][v] = fma(sy4, b4.v[v], py4);
+        P.r[4][v] = fma(sz5, b5.v[v], pz5);
+        P.r[5][v] = fma(sz6, b6.v[v], pz6);
     }
     if constexpr (MODE != 0) {
         P.out_hot = P.out_cold = 0.0;
@@ -238,13 +241,13 @@ __device__ __forceinline__ void pull_mom(const Cell<real> &c, int xv, int y, int
     real left, right;
     if (x0 == 0) {
         if (c.per[0]) left = xl.haveL ? gotL : gplus(sT[base + nx - 1], sX[base + nx - 1]);
-        else left = c.sgn[0] * mine2;
+        else left = c.sgn[0] * mine2 + c.phi[0][0];
     } else {
         left = xl.haveL ? gotL : gplus(sT[base - 1], sX[base - 1]);
     }
     if (x0 + VEC == nx) {
         if (c.per[0]) right = xl.haveR ? gotR : gminus(sT[base - x0], sX[base - x0]);
-        else right = c.sgn[0] * mine1;
+        else right = c.sgn[0] * mine1 + c.phi[0][1];
     } else {
         right = xl.haveR ? gotR : gminus(sT[base + VEC], sX[base + VEC]);
     }
@@ -258,10 +261,10 @@ __device__ __forceinline__ void pull_mom(const Cell<real> &c, int xv, int y, int
         P.f0[v] = Tc.v[v] * real(0.25);
         P.r[0][v] = (v == 0) ? left : gplus(Tc.v[v - 1], Xc.v[v - 1]);
         P.r[1][v] = (v == VEC - 1) ? right : gminus(Tc.v[v + 1], Xc.v[v + 1]);
-        P.r[2][v] = wym ? c.sgn[1] * gminus(Tym.v[v], Yym.v[v]) : gplus(Tym.v[v], Yym.v[v]);
-        P.r[3][v] = wyp ? c.sgn[1] * gplus(Typ.v[v], Yyp.v[v]) : gminus(Typ.v[v], Yyp.v[v]);
-        P.r[4][v] = wzm ? c.sgn[2] * gminus(Tzm.v[v], Zzm.v[v]) : gplus(Tzm.v[v], Zzm.v[v]);
-        P.r[5][v] = wzp ? c.sgn[2] * gplus(Tzp.v[v], Zzp.v[v]) : gminus(Tzp.v[v], Zzp.v[v]);
+        P.r[2][v] = wym ? fma(c.sgn[1], gminus(Tym.v[v], Yym.v[v]), c.phi[1][0]) : gplus(Tym.v[v], Yym.v[v]);
+        P.r[3][v] = wyp ? fma(c.sgn[1], gplus(Typ.v[v], Yyp.v[v]), c.phi[1][1]) : gminus(Typ.v[v], Yyp.v[v]);
+        P.r[4][v] = wzm ? fma(c.sgn[2], gminus(Tzm.v[v], Zzm.v[v]), c.phi[2][0]) : gplus(Tzm.v[v], Zzm.v[v]);
+        P.r[5][v] = wzp ? fma(c.sgn[2], gplus(Tzp.v[v], Zzp.v[v]), c.phi[2][1]) : gminus(Tzp.v[v], Zzp.v[v]);
         if constexpr (MODE != 0) {
             const real t = Tc.v[v];
             P.told[v] = t * real(0.25) + gplus(t, Xc.v[v]) + gminus(t, Xc.v[v]) + gplus(t, Yc.v[v]) +
@@ -289,8 +292,35 @@ __device__ __forceinline__ void pull_mom(const Cell<real> &c, int xv, int y, int
     }
 }
 
-// Collision (shared by both storages), FP64 observables, and the stores.
-// STORAGE 0: 7 populations; 1: 4 moments.
+// General relaxation of the three remaining moments of Eq. 11 (rows 5-7:
+// e = 6 f_0 - sum_{i>0} f_i, p_xx = 2 (f_1 + f_2) - (f_3 + f_4 + f_5 + f_6),
+// p_ww = f_3 + f_4 - f_5 - f_6) with 1/tau_4..6 of Eq. 12 towards their
+// equilibria (3T/4, 0, 0), then f_hat = M^-1 m_hat using the orthogonality of
+// M's rows (squared norms 7, 2, 2, 2, 42, 12, 4).
+template <typename real>
+__device__ __forceinline__ void relax_general(const Cell<real> &c, real f0, real f1, real f2, real f3, real f4,
+                                              real f5, real f6, real T, real hjx, real hjy, real hjz, real *o) {
+    const real e = real(6) * f0 - (((((f1 + f2) + f3) + f4) + f5) + f6);
+    const real pxx = real(2) * (f1 + f2) - (((f3 + f4) + f5) + f6);
+    const real pww = (f3 + f4) - (f5 + f6);
+    const real eh = e - c.srel[0] * (e - real(0.75) * T);
+    const real pxxh = pxx - c.srel[1] * pxx;
+    const real pwwh = pww - c.srel[2] * pww;
+    const real base = T * real(1.0 / 7.0) - eh * real(1.0 / 42.0);
+    const real ax = base + pxxh * real(1.0 / 6.0);
+    const real ay = (base - pxxh * real(1.0 / 12.0)) + pwwh * real(0.25);
+    const real az = (base - pxxh * real(1.0 / 12.0)) - pwwh * real(0.25);
+    o[0] = (T + eh) * real(1.0 / 7.0);
+    o[1] = ax + hjx;
+    o[2] = ax - hjx;
+    o[3] = ay + hjy;
+    o[4] = ay - hjy;
+    o[5] = az + hjz;
+    o[6] = az - hjz;
+}
+
+// Collision (shared by all storages), FP64 observables, and the stores.
+// STORAGE 0: 7 populations; 1: 4 moments; 2: 7 populations, general tau_4..6.
 template <typename real, int VEC, int MODE, int NT, int STORAGE>
 __device__ __forceinline__ void collide_store(const Cell<real> &c, const real *__restrict__ tab, int xv, int y, int z,
                                               bool active, const Pulled<real, VEC> &P, Acc &acc,
@@ -299,6 +329,7 @@ __device__ __forceinline__ void collide_store(const Cell<real> &c, const real *_
     const long long base = ((long long)z * c.ny + y) * c.nx + xv * VEC;
     const real hx = c.h[0], hy = c.h[1], hz = c.h[2];
     Vec<real, VEC> T_, X_, Y_, Z_;
+    Vec<real, VEC> G_[STORAGE == 2 ? Q : 1];  // general relaxation: the seven outputs
 #pragma unroll
     for (int v = 0; v < VEC; v++) {
         const real f0 = P.f0[v];
@@ -315,6 +346,12 @@ __device__ __forceinline__ void collide_store(const Cell<real> &c, const real *_
         X_.v[v] = hjx;
         Y_.v[v] = hjy;
         Z_.v[v] = hjz;
+        if constexpr (STORAGE == 2) {
+            real o[Q];
+            relax_general(c, f0, f1, f2, f3, f4, f5, f6, T, hjx, hjy, hjz, o);
+#pragma unroll
+            for (int i = 0; i < Q; i++) G_[i].v[v] = o[i];
+        }
         if constexpr (MODE != 0) {
             if (active) {
                 const double dT = fabs((double)T - (double)P.told[v]);
@@ -330,9 +367,15 @@ __device__ __forceinline__ void collide_store(const Cell<real> &c, const real *_
                 // in FP64 (the +-h shifts cancel within a node)
                 const double din = (double)f0 + (double)P.r[0][v] + (double)P.r[1][v] + (double)P.r[2][v] +
                                    (double)P.r[3][v] + (double)P.r[4][v] + (double)P.r[5][v];
-                const double dout = (double)(T * real(0.25)) + (double)gplus(T, hjx) + (double)gminus(T, hjx) +
-                                    (double)gplus(T, hjy) + (double)gminus(T, hjy) + (double)gplus(T, hjz) +
-                                    (double)gminus(T, hjz);
+                double dout;
+                if constexpr (STORAGE == 2) {
+                    dout = (double)G_[0].v[v] + (double)G_[1].v[v] + (double)G_[2].v[v] + (double)G_[3].v[v] +
+                           (double)G_[4].v[v] + (double)G_[5].v[v] + (double)G_[6].v[v];
+                } else {
+                    dout = (double)(T * real(0.25)) + (double)gplus(T, hjx) + (double)gminus(T, hjx) +
+                           (double)gplus(T, hjy) + (double)gminus(T, hjy) + (double)gplus(T, hjz) +
+                           (double)gminus(T, hjz);
+                }
                 acc.v[R_LEAK] += dout - din;
                 if (!(dT <= 1e300)) acc.v[R_NONFINITE] += 1.0;
                 else acc.v[R_RESID] = fmax(acc.v[R_RESID], dT);
@@ -377,6 +420,9 @@ __device__ __forceinline__ void collide_store(const Cell<real> &c, const real *_
                     vstore<real, VEC, NS>(d + (2 * a + 1) * N + base, p);
                     vstore<real, VEC, NS>(d + (2 * a + 2) * N + base, m);
                 }
+            } else if constexpr (STORAGE == 2) {
+#pragma unroll
+                for (int i = 0; i < Q; i++) vstore<real, VEC, NS>(d + i * N + base, G_[i]);
             } else {
                 vstore<real, VEC, NS>(d + base, T_);
                 vstore<real, VEC, NS>(d + N + base, X_);
@@ -392,8 +438,8 @@ __device__ __forceinline__ void node_update(const Cell<real> &c, const real *__r
                                             bool active, const XLink &xl, Acc &acc, real *__restrict__ qout,
                                             real qscale) {
     Pulled<real, VEC> P;
-    if constexpr (STORAGE == 0) pull_dist<real, VEC, MODE, NT>(c, xv, y, z, xl, P);
-    else pull_mom<real, VEC, MODE, NT>(c, xv, y, z, xl, P);
+    if constexpr (STORAGE == 1) pull_mom<real, VEC, MODE, NT>(c, xv, y, z, xl, P);
+    else pull_dist<real, VEC, MODE, NT>(c, xv, y, z, xl, P);
     collide_store<real, VEC, MODE, NT, STORAGE>(c, tab, xv, y, z, active, P, acc, qout, qscale);
 }
 

@@ -31,6 +31,9 @@ struct Cell {
     real h[3];                // shift of the gradient-axis populations (eps dT / (2 N_g)), else 0
     int gaxis;
     int storage;              // 0: 7 populations [7][N]; 1: moments (T - T_lin, jhat/2) [4][N]
+    int relax;                // 1: tau_4..6 not all 1 (population storage only)
+    real srel[3];             // 1 / tau_4, 1 / tau_5, 1 / tau_6
+    real phi[3][2];           // lattice heat inflow per link on the low / high face (Neumann), else 0
 };
 
 struct Launch {

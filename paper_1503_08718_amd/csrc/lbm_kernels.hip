@@ -274,6 +274,9 @@ hipError_t launch_step(const Cell<real> &c, const Launch &L, hipStream_t s) {
     if (cc.storage) {
         if (map) launch_step_st<real, 1, 1>(cc, L, grid, block, sh, s);
         else launch_step_st<real, 1, 0>(cc, L, grid, block, sh, s);
+    } else if (cc.relax) {
+        if (map) launch_step_st<real, 2, 1>(cc, L, grid, block, sh, s);
+        else launch_step_st<real, 2, 0>(cc, L, grid, block, sh, s);
     } else {
         if (map) launch_step_st<real, 0, 1>(cc, L, grid, block, sh, s);
         else launch_step_st<real, 0, 0>(cc, L, grid, block, sh, s);
@@ -311,6 +314,7 @@ template <typename real, int VEC>
 static void launch_check_vec(const Cell<real> &c, dim3 grid, dim3 block, size_t sh, int zper, int mode, double *parts,
                              real *q, real qs, hipStream_t s) {
     if (c.storage) launch_check_st<real, VEC, 1>(c, grid, block, sh, zper, mode, parts, q, qs, s);
+    else if (c.relax) launch_check_st<real, VEC, 2>(c, grid, block, sh, zper, mode, parts, q, qs, s);
     else launch_check_st<real, VEC, 0>(c, grid, block, sh, zper, mode, parts, q, qs, s);
 }
 

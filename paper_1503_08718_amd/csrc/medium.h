@@ -22,6 +22,8 @@ struct StopState {
     double kprev = 0.0, dprev = 0.0;
     bool have_prev = false, have_d = false;
     double min_resid = -1.0;
+    int passes = 0;          // consecutive checks that met the k_eff rule
+    bool check_vol = true;   // compare the volume-mean flux (off with imposed side fluxes)
 };
 
 mrtlbm_status fail(mrtlbm_status st, const char *fmt, ...);
@@ -62,6 +64,8 @@ struct mrtlbm_medium {
     int device = 0;
     int cur = 0;               // state in bufA (0) or bufB (1)
     int storage = 0;           // 0: 7 populations per node, 1: 4 moments per node
+    double tau_rest[3] = {1.0, 1.0, 1.0};  // tau_4, tau_5, tau_6 (Eq. 12)
+    double qside[3][2] = {{0, 0}, {0, 0}, {0, 0}};  // imposed inflow on Neumann faces (physical)
     long long steps = 0;
     bool initialised = false;
     mrt::Launch launch{4, 64, 4, 0, 0};
@@ -76,4 +80,5 @@ Cell<real> make_cell(const mrtlbm_medium *m, int cur);
 void drop_graphs(mrtlbm_medium *m);
 void fill_result(const mrtlbm_medium *m, const double *f, mrtlbm_result *out);
 int stop_rule(StopState &ss, const mrtlbm_result &r, double tol, mrtlbm_tol_kind kind);
+bool has_side_flux(const mrtlbm_medium *m);
 }  // namespace mrt

@@ -94,6 +94,17 @@ class Medium:
         check(load().mrtlbm_set_scale(self._h, float(dmax)))
         return self
 
+    def set_side_flux(self, axis: int, q_lo: float, q_hi: float):
+        """Heat flux into the cell through the two Neumann faces of an
+        adiabatic side axis (Eq. 24), in the units of flux()."""
+        check(load().mrtlbm_set_side_flux(self._h, int(axis), float(q_lo), float(q_hi)))
+        return self
+
+    def set_relaxation(self, tau4: float = 1.0, tau5: float = 1.0, tau6: float = 1.0):
+        """tau_4..6 of Eq. 12 (population storage only when not all 1)."""
+        check(load().mrtlbm_set_relaxation(self._h, float(tau4), float(tau5), float(tau6)))
+        return self
+
     def set_launch(self, vec=None, bx=None, by=None, nt=0, map=0):
         if vec is None:
             check(load().mrtlbm_set_launch(self._h, None))

@@ -359,3 +359,112 @@ def test_moment_storage_batch(Medium):
     for x, y, p, q in zip(a, b, ra, rb):
         assert torch.equal(x.temperature(), y.temperature())
         assert p == q
+
+
+# ---------------------------------------------------------------------------
+# general tau_4..6 (Eq. 12) and Neumann faces with a given flux (Eq. 24)
+# ---------------------------------------------------------------------------
+
+TAU_REST = (0.7, 1.6, 1.2)
+
+
+@pytest.mark.parametrize("case", [(12, 7, 5, 3, 0, (0, ADIABATIC, PERIODIC)), (9, 10, 8, 4, 2, (ADIABATIC, PERIODIC, 0)),
+                                  (16, 6, 6, 2, 1, (PERIODIC, 0, ADIABATIC))],
+                         ids=lambda c: "x".join(map(str, c[:3])) + f"_g{c[4]}")
+def test_general_relaxation_matches_oracle(Medium, case):
+    nx, ny, nz, nph, grad, sides = case
+    m = w.random_medium(40 + nph, nx, ny, nz, nph)
+    g = Medium(m.phase, m.k, precision="f64").set_bc(grad, 1.0, 0.0, [SIDE_NAMES[s] for s in sides])
+    g.set_relaxation(*TAU_REST).init()
+    o = Oracle(m.phase, m.k, tau_rest=np.array((1.0,) + TAU_REST))
+    o.set_bc(grad, 1.0, 0.0, sides)
+    o.init()
+    g.step(400)
+    o.step(400)
+    assert field_err(g, o) < 1e-12
+    # the GPU's observables belong to the step after the state it holds
+    kg = g.keff()
+    o.step(1)
+    lf = o.last_fluxes()
+    ng = (nx, ny, nz)[grad]
+    area = nx * ny * nz / ng
+    assert rel(kg["keff_hot"], ng * lf["phi_hot"] / (area * o.scale)) < 1e-10
+    assert rel(kg["keff_cold"], ng * lf["phi_cold"] / (area * o.scale)) < 1e-10
+    # and the relaxation does change the transient: tau_4..6 = 1 differs
+    h = Medium(m.phase, m.k, precision="f64").set_bc(grad, 1.0, 0.0, [SIDE_NAMES[s] for s in sides]).init()
+    h.step(400)
+    assert field_err(h, o) > 1e-9
+
+
+@pytest.mark.parametrize("storage", ["populations", "moments"])
+def test_side_flux_matches_oracle(Medium, storage):
+    m = w.random_medium(51, 11, 9, 7, 3)
+    sides = (0, ADIABATIC, ADIABATIC)
+    g = Medium(m.phase, m.k, precision="f64").set_storage(storage)
+    g.set_bc(0, 0.8, -0.2, [SIDE_NAMES[s] for s in sides])
+    g.set_side_flux(1, 0.04, -0.01).set_side_flux(2, -0.03, 0.05).init()
+    o = Oracle(m.phase, m.k)
+    o.set_bc(0, 0.8, -0.2, sides)
+    o.set_side_flux(1, 0.04, -0.01)
+    o.set_side_flux(2, -0.03, 0.05)
+    o.init()
+    g.step(500)
+    o.step(500)
+    assert field_err(g, o) < 1e-12
+    r = g.keff()
+    area = 9 * 7
+    exp_side = 11 * ((0.04 - 0.01) * 11 * 7 + (-0.03 + 0.05) * 11 * 9) / (1.0 * area)
+    assert rel(r["keff_side"], exp_side) < 1e-14
+
+
+@pytest.mark.parametrize("prec,tau", [("f64", (1.0, 1.0, 1.0)), ("f64", TAU_REST), ("f32", (1.0, 1.0, 1.0))])
+def test_side_flux_of_the_linear_solution_is_exact(Medium, prec, tau):
+    """Homogeneous anisotropic cell, z gradient, x and y Neumann faces carrying
+    the flux of the linear profile: T_lin(z) is the steady state and k = K_zz
+    (any tau_4..6); zero side flux (adiabatic) gives less."""
+    rng = np.random.default_rng(33)
+    K = w.random_spd(rng, 0.3, 1.5)
+    K[0, 2] = K[2, 0] = 0.3
+    K[1, 2] = K[2, 1] = -0.25
+    nx, ny, nz = 16, 12, 24
+    m = w.Medium(np.zeros((nz, ny, nx), np.uint8), w.sym6(K)[None, :])
+    qx, qy = K[0, 2] / nz, K[1, 2] / nz
+    g = Medium(m.phase, m.k, precision=prec).set_bc(2, 1.0, 0.0, ["adiabatic", "adiabatic", "periodic"])
+    g.set_relaxation(*tau).set_side_flux(0, qx, -qx).set_side_flux(1, qy, -qy).init()
+    tol = 1e-9 if prec == "f64" else 1e-5
+    r = g.solve(tol, "keff", 2_000_000, check_every=200)
+    assert r["converged"], r
+    assert abs(r["keff_side"]) < 1e-15
+    assert rel(r["keff"], K[2, 2]) < 10 * tol
+    tlin = 1.0 - (np.arange(nz) + 0.5) / nz
+    assert np.abs(g.temperature().double().cpu().numpy() - tlin[:, None, None]).max() < (1e-7 if prec == "f64" else 1e-4)
+    a = Medium(m.phase, m.k, precision=prec).set_bc(2, 1.0, 0.0, ["adiabatic", "adiabatic", "periodic"]).init()
+    ra = a.solve(tol, "keff", 2_000_000, check_every=200)
+    assert ra["keff"] < K[2, 2] * (1 - 1e-3)
+
+
+def test_side_flux_and_relaxation_errors(Medium):
+    from paper_1503_08718_amd import MrtlbmError
+    from paper_1503_08718_amd.solver import batch_solve
+
+    m = w.random_medium(52, 8, 8, 8, 2)
+    g = Medium(m.phase, m.k, precision="f32").set_bc(0, 1.0, 0.0, ["periodic", "adiabatic", "periodic"])
+    with pytest.raises(MrtlbmError, match="E_BC"):
+        g.set_side_flux(0, 0.1, 0.1)  # gradient axis
+    with pytest.raises(MrtlbmError, match="E_BC"):
+        g.set_side_flux(2, 0.1, 0.1)  # periodic axis
+    with pytest.raises(MrtlbmError, match="E_ARG"):
+        g.set_relaxation(0.5, 1.0, 1.0)  # tau must exceed 1/2
+    g.set_relaxation(1.2, 1.0, 1.0)
+    with pytest.raises(MrtlbmError, match="E_ARG"):
+        g.set_storage("moments")
+    h = Medium(m.phase, m.k, precision="f32").set_storage("moments")
+    with pytest.raises(MrtlbmError, match="E_ARG"):
+        h.set_relaxation(1.2, 1.0, 1.0)
+    g.init()
+    with pytest.raises(MrtlbmError, match="E_ARG"):
+        batch_solve([g], tol=1e-3, kind="keff", max_steps=100, check_every=10)
+    # set_bc clears the side flux
+    g.set_side_flux(1, 0.2, 0.0)
+    g.set_bc(0, 1.0, 0.0, ["periodic", "adiabatic", "periodic"]).init()
+    assert g.keff()["keff_side"] == 0.0

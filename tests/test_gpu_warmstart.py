@@ -62,3 +62,21 @@ def test_rejected_prediction_falls_back_to_zero_start(ws):
     _, r, _, fb = ws.solve_fields([m], tol=1e-3, start="learned", net=net, batch=False)
     assert fb == 1 and r[0]["converged"]
     torch.cuda.synchronize()
+
+
+def test_learned_start_does_not_stop_at_a_turning_point(ws):
+    """A cell of the parametric sweep (128^3, z solve) on which the learned
+    start once made k(t) turn exactly while the energy balance crossed zero,
+    so that a rule of balance plus small change stopped 4.7e-4 away from the
+    answer; the volume-mean flux check and two passing checks in a row must
+    carry the run to the tolerance of an FP64 solve."""
+    assert os.path.exists(MODEL)
+    c = w.sweep_cells(1503, 64)[59]
+    m = w.braid(c["nx"], c["ny"], c["nz"], c["gamma"], c["v"])
+    mz = ws.canonical_media(m)[1]
+    net = ws.Net.from_file(MODEL, batch=1)
+    _, r, _, fb = ws.solve_fields([mz], tol=1e-4, start="learned", net=net, batch=False, storage="moments")
+    _, ref, _, _ = ws.solve_fields([mz], tol=1e-7, start="learned", net=net, batch=False, precision="f64",
+                                   storage="moments", max_steps=20_000_000)
+    assert fb == 0 and r[0]["converged"] and ref[0]["converged"]
+    assert abs(r[0]["keff"] - ref[0]["keff"]) < 1e-4 * ref[0]["keff"], (r[0], ref[0])
