@@ -98,8 +98,7 @@ def parse():
 def _medium(m, prec, args):
     from paper_1503_08718_amd.solver import Medium
 
-    g = Medium(m.phase, m.k, precision=prec, device="cuda:0")
-    g.set_storage(args.storage)
+    g = Medium(m.phase, m.k, precision=prec, device="cuda:0", storage=args.storage)
     if args.launch:
         g.set_launch(*[int(v) for v in args.launch.split(",")])
     elif os.path.exists(args.tune_cache):
@@ -309,7 +308,8 @@ def mode_sweep(args):
     x and z exchanged) in one batched run per start, each to k_eff at --tol.
     Cells per hour count voxelisation, set-up (for the learned start: feature
     resampling, inference and interpolation) and the solves; training is a
-    one-off and not counted.  With --ref-cells K the first K cells are also
+    one-off and not counted; the batched step's shape is autotuned for the
+    cell set inside the timed set-up.  With --ref-cells K the first K cells are also
     solved in FP64 to tol/100 and every start's error is reported on them."""
     import numpy as np
     import torch
@@ -340,7 +340,8 @@ def mode_sweep(args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, res, setup, fb = ws.solve_fields(canon, tol=args.tol, start=start, net=net, batch=True,
-                                            max_steps=args.max_steps, storage=args.storage, keep_fields=False)
+                                            max_steps=args.max_steps, storage=args.storage, keep_fields=False,
+                                            tune=True)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         steps = [r["steps"] for r in res]

@@ -109,8 +109,14 @@ typedef struct { int vec, bx, by, nt, map; } mrtlbm_launch;
 
 /* Bytes of caller-owned device workspace a medium of these sizes needs
  * (two state buffers of 7 reals per node, reduction partials and tables),
- * or 0 for invalid sizes. */
+ * or 0 for invalid sizes.  Enough for either state storage. */
 size_t mrtlbm_workspace_bytes(int nx, int ny, int nz, int nphase, mrtlbm_precision p);
+
+/* The same for one state storage (0: 7 populations per node, 1: 4 moments
+ * per node; see mrtlbm_set_storage), or 0 for invalid arguments.  A medium
+ * created on a workspace of the storage-1 size starts in moment storage and
+ * cannot switch to populations (E_WORKSPACE). */
+size_t mrtlbm_workspace_bytes_storage(int nx, int ny, int nz, int nphase, mrtlbm_precision p, int storage);
 
 /*
  * Create a medium (Sec. 2.2-2.3; Eqs. 12-13 for the per-phase tables).
@@ -119,8 +125,10 @@ size_t mrtlbm_workspace_bytes(int nx, int ny, int nz, int nphase, mrtlbm_precisi
  *   k_host: [nphase][6] = (kxx, kyy, kzz, kxy, kxz, kyz), physical units;
  *       copied.  Each tensor must be symmetric positive definite
  *       (MRTLBM_E_TENSOR).  1 <= nphase <= 256.
- *   workspace_dev: >= mrtlbm_workspace_bytes(...) bytes, 256-byte aligned,
- *       caller-owned, must outlive the medium.
+ *   workspace_dev: >= mrtlbm_workspace_bytes_storage(..., 1) bytes,
+ *       256-byte aligned, caller-owned, must outlive the medium; the medium
+ *       starts in population storage when the workspace holds it
+ *       (>= mrtlbm_workspace_bytes), otherwise in moment storage.
  *   hip_stream: a hipStream_t, or NULL for the default stream.
  * Defaults: dmax = 1, gradient along x with T = 1 on the x = 0 face and
  * T = 0 on the far x face, periodic y and z, state not initialised.
@@ -201,7 +209,8 @@ mrtlbm_status mrtlbm_flux(mrtlbm_medium *m, void *q_dev);
  *      read and written.  The populations are recomputed from them with the
  *      operations that produce them in storage 0, so both storages give
  *      bit-identical temperature and flux fields.
- * Invalidates the state. */
+ * Invalidates the state.  E_WORKSPACE when the workspace is too small for
+ * the storage, E_ARG for storage 1 with tau_4..6 other than 1. */
 mrtlbm_status mrtlbm_set_storage(mrtlbm_medium *m, int storage);
 
 /* Values per node of the state: 7 (storage 0) or 4 (storage 1). */
@@ -256,12 +265,28 @@ size_t mrtlbm_batch_workspace_bytes(mrtlbm_medium *const *cells, int n);
  * covers all still-active cells (a table of row tiles), and the steps between
  * checks are replayed as one hip graph; a cell leaves the table when its own
  * stop rule holds.  All cells must share the precision and the stream of
- * cells[0].  out: [n].  Returns MRTLBM_OK when every cell converged,
+ * cells[0]; the step's shape (vec, bx * by threads per row tile, nt, map)
+ * is cells[0]'s launch shape (see mrtlbm_batch_autotune).  out: [n].
+ * Returns MRTLBM_OK when every cell converged,
  * MRTLBM_NOT_CONVERGED if any ran out of steps.  Synchronises.
  */
 mrtlbm_status mrtlbm_batch_solve(mrtlbm_medium *const *cells, int n, double tol, mrtlbm_tol_kind kind,
                                  long long max_steps, int check_every, void *workspace_dev,
                                  size_t workspace_bytes, mrtlbm_result *out);
+
+/*
+ * Pick the batched step's shape for exactly this set of media: times every
+ * valid (vec, threads per row tile in {64, 128, 256}, cache policy nt, tile
+ * order map) on all cells together, from zero states, over about 2e10
+ * algorithmic bytes each, and stores the fastest in cells[0]'s launch shape,
+ * which mrtlbm_batch_solve uses (map = 1: each XCD sweeps one contiguous
+ * eighth of the tile table).  Overwrites the states: every cell is left
+ * uninitialised with its step counter at 0, so call it before mrtlbm_init.
+ * Same requirements and workspace as mrtlbm_batch_solve.  best may be NULL.
+ * Synchronises.
+ */
+mrtlbm_status mrtlbm_batch_autotune(mrtlbm_medium *const *cells, int n, void *workspace_dev,
+                                    size_t workspace_bytes, mrtlbm_launch *best);
 
 #ifdef __cplusplus
 }

@@ -101,6 +101,7 @@ def load():
     LP = ctypes.POINTER(Launch)
     sig = {
         "mrtlbm_workspace_bytes": (SZ, [I, I, I, I, I]),
+        "mrtlbm_workspace_bytes_storage": (SZ, [I, I, I, I, I, I]),
         "mrtlbm_create": (I, [I, I, I, P, ctypes.POINTER(ctypes.c_double), I, I, P, SZ, P, PP]),
         "mrtlbm_set_bc": (I, [P, I, D, D, ctypes.POINTER(ctypes.c_int)]),
         "mrtlbm_set_scale": (I, [P, D]),
@@ -125,6 +126,7 @@ def load():
         "mrtlbm_last_error": (ctypes.c_char_p, []),
         "mrtlbm_batch_workspace_bytes": (SZ, [PP, I]),
         "mrtlbm_batch_solve": (I, [PP, I, D, I, LL, I, P, SZ, RP]),
+        "mrtlbm_batch_autotune": (I, [PP, I, P, SZ, ctypes.POINTER(Launch)]),
     }
     F = ctypes.c_float
     FP = ctypes.POINTER(ctypes.c_float)

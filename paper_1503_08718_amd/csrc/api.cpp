@@ -141,25 +141,35 @@ static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 size_t mrt::partial_capacity(int nx, int ny) { return (size_t)((nx + 15) / 16) * (size_t)ny + 4096; }
 
-static bool layout(int nx, int ny, int nz, int nphase, mrtlbm_precision p, size_t off[5], size_t *total) {
+// the small arrays first, so that their offsets do not depend on the state
+// storage; then the two state buffers of `values` reals per node
+static bool layout(int nx, int ny, int nz, int nphase, mrtlbm_precision p, int values, size_t off[5],
+                   size_t *total) {
     if (nx < 1 || ny < 1 || nz < 1 || nphase < 1 || nphase > 256) return false;
     if (nz > 65535 || (long long)ny > 65535LL * 16) return false;
     const size_t rs = (p == MRTLBM_F64) ? 8 : 4;
     const size_t N = (size_t)nx * ny * nz;
     size_t o = 0;
-    off[0] = o; o = align256(o + Q * N * rs);                          // buffer A
-    off[1] = o; o = align256(o + Q * N * rs);                          // buffer B
     off[2] = o; o = align256(o + partial_capacity(nx, ny) * NRED * 8); // partials
     off[3] = o; o = align256(o + 16 * 8);                              // final reduction
     off[4] = o; o = align256(o + (size_t)nphase * TABW * rs);          // phase tables
+    off[0] = o; o = align256(o + values * N * rs);                     // buffer A
+    off[1] = o; o = align256(o + values * N * rs);                     // buffer B
     *total = o;
     return true;
 }
 
-extern "C" size_t mrtlbm_workspace_bytes(int nx, int ny, int nz, int nphase, mrtlbm_precision p) {
+static int state_values_of(int storage) { return storage ? 4 : Q; }
+
+extern "C" size_t mrtlbm_workspace_bytes_storage(int nx, int ny, int nz, int nphase, mrtlbm_precision p,
+                                                 int storage) {
     size_t off[5], total;
-    if (p != MRTLBM_F32 && p != MRTLBM_F64) return 0;
-    return layout(nx, ny, nz, nphase, p, off, &total) ? total : 0;
+    if ((p != MRTLBM_F32 && p != MRTLBM_F64) || (storage != 0 && storage != 1)) return 0;
+    return layout(nx, ny, nz, nphase, p, state_values_of(storage), off, &total) ? total : 0;
+}
+
+extern "C" size_t mrtlbm_workspace_bytes(int nx, int ny, int nz, int nphase, mrtlbm_precision p) {
+    return mrtlbm_workspace_bytes_storage(nx, ny, nz, nphase, p, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -279,12 +289,16 @@ extern "C" mrtlbm_status mrtlbm_create(int nx, int ny, int nz, const unsigned ch
     if (!out) return fail(MRTLBM_E_ARG, "out is NULL");
     *out = nullptr;
     if (p != MRTLBM_F32 && p != MRTLBM_F64) return fail(MRTLBM_E_ARG, "bad precision %d", (int)p);
-    size_t off[5], total;
-    if (!layout(nx, ny, nz, nphase, p, off, &total))
+    size_t off[5], total, off7[5], total7;
+    if (!layout(nx, ny, nz, nphase, p, 4, off, &total) || !layout(nx, ny, nz, nphase, p, Q, off7, &total7))
         return fail(MRTLBM_E_ARG, "bad sizes nx=%d ny=%d nz=%d nphase=%d", nx, ny, nz, nphase);
     if (!phase_dev || !k_host) return fail(MRTLBM_E_ARG, "phase_dev or k_host is NULL");
     if (!workspace_dev || workspace_bytes < total)
         return fail(MRTLBM_E_WORKSPACE, "workspace of %zu bytes, need %zu", workspace_bytes, total);
+    // a workspace that holds 7 populations per node starts in population
+    // storage, a smaller one (moments only) in moment storage
+    const int storage = workspace_bytes >= total7 ? 0 : 1;
+    if (!storage) memcpy(off, off7, sizeof(off));
     if (((uintptr_t)workspace_dev) & 255) return fail(MRTLBM_E_WORKSPACE, "workspace not 256-byte aligned");
     for (int q = 0; q < nphase; q++) {
         double K[9];
@@ -311,6 +325,7 @@ extern "C" mrtlbm_status mrtlbm_create(int nx, int ny, int nz, const unsigned ch
     m->partials = (double *)(w + off[2]);
     m->final8 = (double *)(w + off[3]);
     m->tab = w + off[4];
+    m->storage = storage;
     m->pcap = partial_capacity(nx, ny);
     m->stream = (hipStream_t)hip_stream;
     m->launch = default_launch(m);
@@ -711,6 +726,12 @@ extern "C" mrtlbm_status mrtlbm_set_storage(mrtlbm_medium *m, int storage) {
     if (storage != 0 && storage != 1) return fail(MRTLBM_E_ARG, "storage must be 0 or 1");
     if (storage == 1 && (m->tau_rest[0] != 1.0 || m->tau_rest[1] != 1.0 || m->tau_rest[2] != 1.0))
         return fail(MRTLBM_E_ARG, "moment storage holds only tau_4 = tau_5 = tau_6 = 1");
+    size_t off[5], total;
+    layout(m->nx, m->ny, m->nz, m->nphase, m->prec, state_values_of(storage), off, &total);
+    if (total > m->ws_bytes)
+        return fail(MRTLBM_E_WORKSPACE, "workspace of %zu bytes, storage %d needs %zu", m->ws_bytes, storage, total);
+    m->bufA = (char *)m->ws + off[0];
+    m->bufB = (char *)m->ws + off[1];
     m->storage = storage;
     m->initialised = false;
     drop_graphs(m);

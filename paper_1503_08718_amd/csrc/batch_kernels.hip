@@ -26,13 +26,18 @@ __device__ __forceinline__ XLink packed_links(int xv, int nxv) {
     return xl;
 }
 
-// tile = (cell, z-plane, first row y0, number of rows)
+// tile = (cell, z-plane, first row y0, number of rows).  chunk > 0: the
+// table holds 8 * chunk tiles and block b takes tile (b % 8) * chunk + b / 8,
+// so that each XCD (blocks go to the 8 XCDs round robin) sweeps one
+// contiguous eighth of the table and finds the neighbouring rows and planes
+// it pulls in its own L2.
 template <typename real, int VEC, int MODE, int NT, int ST>
 __global__ void __launch_bounds__(256) k_batch(const Cell<real> *__restrict__ cells, const int4 *__restrict__ tiles,
-                                               int parity, double *partials) {
+                                               int parity, int chunk, double *partials) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     real *tab = reinterpret_cast<real *>(smem_raw);
-    const int4 tile = tiles[blockIdx.x];
+    const int ti = chunk ? (int)(blockIdx.x % 8u) * chunk + (int)(blockIdx.x / 8u) : (int)blockIdx.x;
+    const int4 tile = tiles[ti];
     Cell<real> c = cells[tile.x];
     if (parity) {
         const real *t = c.src;
@@ -52,7 +57,7 @@ __global__ void __launch_bounds__(256) k_batch(const Cell<real> *__restrict__ ce
     Acc acc;
     acc.zero();
     node_update<real, VEC, MODE, NT, ST>(c, tab, xv, y, z, active, packed_links(xv, c.nxv), acc, nullptr, real(0));
-    if constexpr (MODE == 1) block_reduce_store(acc, partials + (long long)blockIdx.x * NRED);
+    if constexpr (MODE == 1) block_reduce_store(acc, partials + (long long)ti * NRED);
 }
 
 // one block per cell: fixed-order sum of that cell's tile partials
@@ -81,30 +86,39 @@ __global__ void __launch_bounds__(256) k_batch_reduce(const double *__restrict__
 
 template <typename real, int VEC, int ST>
 static void launch_batch_st(const Cell<real> *cells, const int4 *tiles, int ntiles, int threads, size_t sh, int parity,
-                            bool check, int nt, double *partials, hipStream_t s) {
+                            bool check, int nt, int chunk, double *partials, hipStream_t s) {
     const dim3 g(ntiles), b(threads);
-    if (check) hipLaunchKernelGGL((k_batch<real, VEC, 1, 0, ST>), g, b, sh, s, cells, tiles, parity, partials);
-    else if (nt == 3) hipLaunchKernelGGL((k_batch<real, VEC, 0, 3, ST>), g, b, sh, s, cells, tiles, parity, partials);
-    else if (nt == 2) hipLaunchKernelGGL((k_batch<real, VEC, 0, 2, ST>), g, b, sh, s, cells, tiles, parity, partials);
-    else if (nt == 1) hipLaunchKernelGGL((k_batch<real, VEC, 0, 1, ST>), g, b, sh, s, cells, tiles, parity, partials);
-    else hipLaunchKernelGGL((k_batch<real, VEC, 0, 0, ST>), g, b, sh, s, cells, tiles, parity, partials);
+    if (check) hipLaunchKernelGGL((k_batch<real, VEC, 1, 0, ST>), g, b, sh, s, cells, tiles, parity, chunk, partials);
+    else if (nt == 3)
+        hipLaunchKernelGGL((k_batch<real, VEC, 0, 3, ST>), g, b, sh, s, cells, tiles, parity, chunk, partials);
+    else if (nt == 2)
+        hipLaunchKernelGGL((k_batch<real, VEC, 0, 2, ST>), g, b, sh, s, cells, tiles, parity, chunk, partials);
+    else if (nt == 1)
+        hipLaunchKernelGGL((k_batch<real, VEC, 0, 1, ST>), g, b, sh, s, cells, tiles, parity, chunk, partials);
+    else hipLaunchKernelGGL((k_batch<real, VEC, 0, 0, ST>), g, b, sh, s, cells, tiles, parity, chunk, partials);
 }
 
 template <typename real, int VEC>
 static void launch_batch_vec(const Cell<real> *cells, const int4 *tiles, int ntiles, int threads, size_t sh, int parity,
-                             bool check, int nt, int storage, double *partials, hipStream_t s) {
-    if (storage) launch_batch_st<real, VEC, 1>(cells, tiles, ntiles, threads, sh, parity, check, nt, partials, s);
-    else launch_batch_st<real, VEC, 0>(cells, tiles, ntiles, threads, sh, parity, check, nt, partials, s);
+                             bool check, int nt, int chunk, int storage, double *partials, hipStream_t s) {
+    if (storage) launch_batch_st<real, VEC, 1>(cells, tiles, ntiles, threads, sh, parity, check, nt, chunk, partials, s);
+    else launch_batch_st<real, VEC, 0>(cells, tiles, ntiles, threads, sh, parity, check, nt, chunk, partials, s);
 }
 
 template <typename real>
 hipError_t launch_batch(const Cell<real> *cells, const int4 *tiles, int ntiles, int vec, int threads, int max_nphase,
-                        int parity, bool check, int nt, int storage, double *partials, hipStream_t s) {
+                        int parity, bool check, int nt, int chunk, int storage, double *partials, hipStream_t s) {
     const size_t sh = sizeof(real) * TABW * max_nphase;
     switch (vec) {
-        case 4: launch_batch_vec<real, 4>(cells, tiles, ntiles, threads, sh, parity, check, nt, storage, partials, s); break;
-        case 2: launch_batch_vec<real, 2>(cells, tiles, ntiles, threads, sh, parity, check, nt, storage, partials, s); break;
-        default: launch_batch_vec<real, 1>(cells, tiles, ntiles, threads, sh, parity, check, nt, storage, partials, s); break;
+        case 4:
+            launch_batch_vec<real, 4>(cells, tiles, ntiles, threads, sh, parity, check, nt, chunk, storage, partials, s);
+            break;
+        case 2:
+            launch_batch_vec<real, 2>(cells, tiles, ntiles, threads, sh, parity, check, nt, chunk, storage, partials, s);
+            break;
+        default:
+            launch_batch_vec<real, 1>(cells, tiles, ntiles, threads, sh, parity, check, nt, chunk, storage, partials, s);
+            break;
     }
     return hipGetLastError();
 }
@@ -114,9 +128,9 @@ hipError_t launch_batch_reduce(const double *partials, const int *start, int nce
     return hipGetLastError();
 }
 
-template hipError_t launch_batch<float>(const Cell<float> *, const int4 *, int, int, int, int, int, bool, int, int,
+template hipError_t launch_batch<float>(const Cell<float> *, const int4 *, int, int, int, int, int, bool, int, int, int,
                                         double *, hipStream_t);
 template hipError_t launch_batch<double>(const Cell<double> *, const int4 *, int, int, int, int, int, bool, int, int,
-                                         double *, hipStream_t);
+                                         int, double *, hipStream_t);
 
 }  // namespace mrt

@@ -17,6 +17,7 @@ from ._lib import ADIABATIC, F32, F64, PERIODIC, TOL_KEFF, TOL_MAXDT, Launch, Re
 
 _SIDES = {"periodic": PERIODIC, "adiabatic": ADIABATIC, PERIODIC: PERIODIC, ADIABATIC: ADIABATIC}
 _KINDS = {"maxdt": TOL_MAXDT, "keff": TOL_KEFF, TOL_MAXDT: TOL_MAXDT, TOL_KEFF: TOL_KEFF}
+_STORAGE = {"populations": 0, "moments": 1, 0: 0, 1: 1}
 _PREC = {"f32": F32, "float32": F32, torch.float32: F32, F32: F32,
          "f64": F64, "float64": F64, torch.float64: F64, F64: F64}
 
@@ -32,10 +33,13 @@ class Medium:
     """One voxel medium on one GPU.
 
     phase: uint8 array/tensor (nz, ny, nx); k: (nphase, 6) float64 tensors
-    (kxx, kyy, kzz, kxy, kxz, kyz) in physical units.
+    (kxx, kyy, kzz, kxy, kxz, kyz) in physical units.  storage=None sizes
+    the workspace for either state storage (starting with populations);
+    "moments" allocates only what moment storage needs (4 of 7 values per
+    node) and the medium cannot switch to populations.
     """
 
-    def __init__(self, phase, k, precision="f32", device="cuda:0"):
+    def __init__(self, phase, k, precision="f32", device="cuda:0", storage=None):
         L = load()
         self.device = torch.device(device)
         if isinstance(phase, np.ndarray):
@@ -47,7 +51,10 @@ class Medium:
         self.nphase = self.k.shape[0]
         self.prec = _PREC[precision]
         self.dtype = torch.float64 if self.prec == F64 else torch.float32
-        nbytes = L.mrtlbm_workspace_bytes(nx, ny, nz, self.nphase, self.prec)
+        if storage is None:
+            nbytes = L.mrtlbm_workspace_bytes(nx, ny, nz, self.nphase, self.prec)
+        else:
+            nbytes = L.mrtlbm_workspace_bytes_storage(nx, ny, nz, self.nphase, self.prec, _STORAGE[storage])
         if nbytes == 0:
             raise ValueError(f"invalid medium sizes {self.shape} / nphase {self.nphase}")
         with torch.cuda.device(self.device):
@@ -59,6 +66,8 @@ class Medium:
                               self.stream.cuda_stream, ctypes.byref(h)))
         self._h = h
         self.grad_axis, self.t_hot, self.t_cold = 0, 1.0, 0.0
+        if storage is not None:
+            self.set_storage(storage)
 
     # -- lifetime ---------------------------------------------------------
     def close(self):
@@ -86,8 +95,7 @@ class Medium:
 
     def set_storage(self, storage):
         """"populations" (7 values per node) or "moments" (4 values per node)."""
-        v = {"populations": 0, "moments": 1, 0: 0, 1: 1}[storage]
-        check(load().mrtlbm_set_storage(self._h, v))
+        check(load().mrtlbm_set_storage(self._h, _STORAGE[storage]))
         return self
 
     def set_scale(self, dmax: float):
@@ -205,3 +213,21 @@ def batch_solve(media, tol: float = 1e-4, kind="keff", max_steps: int = 10**7, c
     del ws
     out = [r.to_dict() for r in res]
     return out, _lib.STATUS[st]
+
+
+def batch_autotune(media) -> dict:
+    """Choose the batched step's shape for these media (mrtlbm_batch_autotune).
+    Overwrites their states: call init() on every medium afterwards."""
+    L = load()
+    n = len(media)
+    arr = (ctypes.c_void_p * n)(*[m.handle.value for m in media])
+    nbytes = L.mrtlbm_batch_workspace_bytes(arr, n)
+    if nbytes == 0:
+        raise ValueError("batch workspace size is zero (bad media list)")
+    dev = media[0].device
+    with torch.cuda.device(dev):
+        ws, wptr = _aligned_bytes(nbytes, dev)
+    best = Launch()
+    check(L.mrtlbm_batch_autotune(arr, n, wptr, nbytes, ctypes.byref(best)))
+    del ws
+    return dict(vec=best.vec, bx=best.bx, by=best.by, nt=best.nt, map=best.map)

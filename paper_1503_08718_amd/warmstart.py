@@ -315,20 +315,24 @@ def linear_start(shape, device, dtype=torch.float32):
 
 
 def solve_fields(media, tol=1e-4, check_every=1000, max_steps=5_000_000, start="linear", net=None, batch=True,
-                 precision="f32", storage="populations", keep_fields=True):
+                 precision="f32", storage="populations", keep_fields=True, tune=False):
     """Steady x-gradient fields of canonical media (periodic sides).
 
-    start: "zero", "linear" or "learned" (needs net).  Returns (temperature
+    start: "zero", "linear" or "learned" (needs net); tune: pick the batched
+    step's shape for this set first (batch only).  Returns (temperature
     tensors or None, results, setup seconds, number of rejected predictions)."""
-    from .solver import Medium, batch_solve
+    from .solver import Medium, batch_autotune, batch_solve
 
     cells = []
     t0 = time.perf_counter()
     fallbacks = 0
     for m in media:
-        g = Medium(m.phase, m.k, precision=precision)
-        g.set_storage(storage)
+        g = Medium(m.phase, m.k, precision=precision, storage=storage)
         g.set_bc(0, 1.0, 0.0, ("periodic",) * 3)
+        cells.append(g)
+    if batch and tune:
+        batch_autotune(cells)
+    for m, g in zip(media, cells):
         if start == "zero":
             g.init()
         elif start == "linear":
@@ -340,7 +344,6 @@ def solve_fields(media, tol=1e-4, check_every=1000, max_steps=5_000_000, start="
                 g.init()
             else:
                 g.init(T0.to(g.dtype), flux=True)
-        cells.append(g)
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
     if batch:

@@ -48,6 +48,11 @@ def test_workspace_bytes(lib):
     assert lib.mrtlbm_workspace_bytes(4, 4, 4, 0, _lib.F32) == 0
     assert lib.mrtlbm_workspace_bytes(4, 4, 4, 300, _lib.F32) == 0
     assert lib.mrtlbm_workspace_bytes(4, 4, 4, 2, 7) == 0
+    # moment storage: two buffers of 4 values per node
+    m32 = lib.mrtlbm_workspace_bytes_storage(128, 128, 128, 5, _lib.F32, 1)
+    assert 2 * 4 * n * 4 <= m32 < 2 * 4 * n * 4 * 1.03
+    assert lib.mrtlbm_workspace_bytes_storage(128, 128, 128, 5, _lib.F32, 0) == f32
+    assert lib.mrtlbm_workspace_bytes_storage(4, 4, 4, 2, _lib.F32, 2) == 0
 
 
 def test_errors_before_any_device_work(lib):
@@ -61,7 +66,8 @@ def test_errors_before_any_device_work(lib):
     ws = lib.mrtlbm_workspace_bytes(4, 4, 4, 1, _lib.F32)
     st = lib.mrtlbm_create(4, 4, 4, fake, bad, 1, _lib.F32, fake, ws, None, ctypes.byref(out))
     assert st == -2
-    st = lib.mrtlbm_create(4, 4, 4, fake, k, 1, _lib.F32, fake, ws - 1, None, ctypes.byref(out))
+    wsm = lib.mrtlbm_workspace_bytes_storage(4, 4, 4, 1, _lib.F32, 1)
+    st = lib.mrtlbm_create(4, 4, 4, fake, k, 1, _lib.F32, fake, wsm - 1, None, ctypes.byref(out))
     assert st == -7
     assert lib.mrtlbm_set_bc(None, 0, 1.0, 0.0, None) == -1
     assert lib.mrtlbm_step(None, 1) == -1

@@ -81,3 +81,37 @@ def test_batch_sweep_cells_fp32(api):
     assert st == "OK"
     for r in res:
         assert r["converged"] and r["keff"] > 0.2
+
+
+@pytest.mark.parametrize("storage", ["populations", "moments"])
+def test_xcd_tile_order_and_batch_autotune(api, storage):
+    """The XCD-aware tile order (map) and every shape the batch autotuner
+    may pick leave the arithmetic alone: states stay bit-identical to
+    stepping each cell alone."""
+    import torch
+
+    def cells():
+        out = _cells(api, "f32")
+        for c in out:
+            c.set_storage(storage).init()
+        return out
+
+    alone = cells()
+    for c in alone:
+        c.step(600)
+    for mp in (0, 1):
+        batch = cells()
+        batch[0].set_launch(1, 64, 2, 0, mp)  # vec 1: the odd-nx cell allows no more
+        api.batch_solve(batch, tol=1e-30, kind="keff", max_steps=600, check_every=100)
+        for b, a in zip(batch, alone):
+            assert torch.equal(b.state_get(), a.state_get())
+    batch = cells()
+    best = api.batch_autotune(batch)
+    assert best["vec"] == 1 and best["bx"] * best["by"] in (64, 128, 256) and best["map"] in (0, 1)
+    assert batch[0].info()["launch"] == (best["vec"], best["bx"], best["by"], best["nt"], best["map"])
+    for c in batch:
+        c.init()
+    res, st = api.batch_solve(batch, tol=1e-30, kind="keff", max_steps=600, check_every=100)
+    assert all(r["steps"] == 600 for r in res)
+    for b, a in zip(batch, alone):
+        assert torch.equal(b.state_get(), a.state_get())
