@@ -206,9 +206,15 @@ mrtlbm_status mrtlbm_flux(mrtlbm_medium *m, void *q_dev);
  *      real [7][nz][ny][nx] (T_lin: the linear profile between the walls);
  *   1: the moments (T - T_lin(x), jhat_x/2, jhat_y/2, jhat_z/2),
  *      real [4][nz][ny][nx]: 4 instead of 7 values per node and per step
- *      read and written.  The populations are recomputed from them with the
- *      operations that produce them in storage 0, so both storages give
- *      bit-identical temperature and flux fields.
+ *      read and written.  In FP64 the populations are recomputed from them
+ *      with the operations that produce them in storage 0, so both storages
+ *      give bit-identical fields.  In FP32 they are recomputed exactly (in
+ *      FP64), so a step rounds only the new T and jhat/2; storage 0 has to
+ *      round each population and the two agree to FP32 noise.
+ *   FP32 rounding (both storages) is dithered: values computed in FP64 are
+ *      rounded up with probability equal to the discarded fraction, with
+ *      random bits hashed from the value and the node, a deterministic
+ *      function of the state.
  * Invalidates the state.  E_WORKSPACE when the workspace is too small for
  * the storage, E_ARG for storage 1 with tau_4..6 other than 1. */
 mrtlbm_status mrtlbm_set_storage(mrtlbm_medium *m, int storage);

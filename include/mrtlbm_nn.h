@@ -8,7 +8,8 @@
  * Conventions:
  *   - Activations are BF16 (raw 16-bit patterns, `void *`), channels-last
  *     [n][d][h][w][c] with d = z, h = y, w = x.  Channel counts are multiples
- *     of 8 (inputs) and 16 (outputs of a convolution).
+ *     of 8 (inputs) and 16 (outputs of a convolution); a convolution takes
+ *     n d h w < 2^31 voxels (E_ARG otherwise).
  *   - A 3x3x3 convolution's weights are BF16 [cout][kpad] with
  *     k = tap * cin + ci, tap = (dz * 3 + dy) * 3 + dx for offsets -1, 0, +1
  *     (cross-correlation), kpad = mrtlbm_nn_kpad(cin), entries k >= 27 cin

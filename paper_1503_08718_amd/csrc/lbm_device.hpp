@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "lbm_internal.h"
 
@@ -196,9 +197,10 @@ __device__ __forceinline__ void pull_dist(const Cell<real> &c, int xv, int y, in
 
 // Moment storage: state [4][N] = (T - T_lin, jhat_x / 2, jhat_y / 2, jhat_z / 2).
 // With tau_4 = tau_5 = tau_6 = 1 the post-collision populations are
-// g_0 = T/4 and g_{2a+1, 2a+2} = T/8 +- jhat_a/2, recomputed here with the
-// very operations that produced them in distribution storage, so both
-// storages evolve bit for bit alike.
+// g_0 = T/4 and g_{2a+1, 2a+2} = T/8 +- jhat_a/2.  In FP64 they are
+// recomputed here with the very operations that produce them in population
+// storage, so the two storages evolve bit for bit alike; the FP32 moment
+// path (pull_mom_exact below) keeps them exact instead.
 template <typename real>
 __device__ __forceinline__ real gplus(real T, real z) { return fma(T, real(0.125), z); }
 template <typename real>
@@ -292,6 +294,49 @@ __device__ __forceinline__ void pull_mom(const Cell<real> &c, int xv, int y, int
     }
 }
 
+// FP32 state: round values computed in FP64 to FP32 with a dither.
+// Close to steady state the slowest mode changes a node's T by less than
+// half an FP32 ulp per step; round-to-nearest then drops every such
+// increment and the iteration stalls at a fixed point of the rounded map whose
+// error grows like the mode's relaxation time (N_g^2).  Where the field is
+// smooth, round-to-nearest also makes neighbouring nodes err the same way, a
+// coherent energy source.  Rounding up with probability equal to the
+// discarded fraction keeps every increment in expectation and decorrelates
+// the errors.  The random bits are a hash of the value and of a per-node,
+// per-quantity key, so the result is a deterministic function of the state
+// (independent of launch shape, batching and storage); they change whenever
+// the state does.  Mechanism: add 29 random bits below the 23 FP32 fraction
+// bits of the FP64 value and truncate; the truncated value is exact in FP32.
+// one multiply carries every input bit into the top bits used below
+__device__ __forceinline__ unsigned mix32(unsigned a) {
+    a ^= a >> 16;
+    a *= 0x7feb352du;
+    a ^= a >> 15;
+    return a;
+}
+
+__device__ __forceinline__ float dither_to_float(double x, unsigned long long node) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const unsigned key = mix32((unsigned)b ^ (unsigned)(b >> 32) ^ ((unsigned)node * 0x9E3779B9u) ^
+                               (unsigned)(node >> 32));
+    const unsigned long long r = (unsigned long long)(key >> 3);  // 29 bits
+    return (float)__longlong_as_double((long long)((b + r) & ~0x1FFFFFFFull));
+}
+
+// Post-collision population T/8 +- jhat_a/2 as population storage keeps it:
+// FP64 rounds to nearest; FP32 is dithered (the sum is exact in FP64), so
+// that T/8 is not lost, always in the same direction, where it falls below
+// half an ulp of jhat_a/2.  a = axis, s = 0 (+) or 1 (-).
+template <typename real>
+__device__ __forceinline__ real out_pop(real T, real hj, long long node, int a, int s) {
+    if constexpr (sizeof(real) == 4) {
+        const double e = s ? (double)T * 0.125 - (double)hj : (double)T * 0.125 + (double)hj;
+        return dither_to_float(e, ((unsigned long long)node * 8ull + (unsigned long long)(2 * a + s)) ^ (1ull << 62));
+    } else {
+        return s ? gminus(T, hj) : gplus(T, hj);
+    }
+}
+
 // General relaxation of the three remaining moments of Eq. 11 (rows 5-7:
 // e = 6 f_0 - sum_{i>0} f_i, p_xx = 2 (f_1 + f_2) - (f_3 + f_4 + f_5 + f_6),
 // p_ww = f_3 + f_4 - f_5 - f_6) with 1/tau_4..6 of Eq. 12 towards their
@@ -336,12 +381,35 @@ __device__ __forceinline__ void collide_store(const Cell<real> &c, const real *_
         const real f1 = P.r[0][v] + hx, f2 = P.r[1][v] - hx;
         const real f3 = P.r[2][v] + hy, f4 = P.r[3][v] - hy;
         const real f5 = P.r[4][v] + hz, f6 = P.r[5][v] - hz;
-        const real T = f0 + f1 + f2 + f3 + f4 + f5 + f6;
-        const real jx = f1 - f2, jy = f3 - f4, jz = f5 - f6;
         const real *tb = tab + P.ph[v] * TABW;  // half of (I - tau^-1)
-        const real hjx = fma(tb[4], jz, fma(tb[3], jy, tb[0] * jx));
-        const real hjy = fma(tb[5], jz, fma(tb[1], jy, tb[3] * jx));
-        const real hjz = fma(tb[2], jz, fma(tb[5], jy, tb[4] * jx));
+        real T, jx, jy, jz, hjx, hjy, hjz;
+        if constexpr (sizeof(real) == 4) {
+            // T and jhat/2 from the FP32 inputs in FP64 (exact sums and
+            // differences), each dithered to FP32 with its own random bits
+            const unsigned long long key = (unsigned long long)(base + v) * 4ull;
+            const double T64 = (((((((double)f0 + (double)f1) + (double)f2) + (double)f3) + (double)f4) +
+                                 (double)f5) + (double)f6);
+            const double jx64 = (double)f1 - (double)f2, jy64 = (double)f3 - (double)f4,
+                         jz64 = (double)f5 - (double)f6;
+            const double hx64 = fma((double)tb[4], jz64, fma((double)tb[3], jy64, (double)tb[0] * jx64));
+            const double hy64 = fma((double)tb[5], jz64, fma((double)tb[1], jy64, (double)tb[3] * jx64));
+            const double hz64 = fma((double)tb[2], jz64, fma((double)tb[5], jy64, (double)tb[4] * jx64));
+            T = dither_to_float(T64, key);
+            hjx = dither_to_float(hx64, key + 1);
+            hjy = dither_to_float(hy64, key + 2);
+            hjz = dither_to_float(hz64, key + 3);
+            jx = (real)jx64;
+            jy = (real)jy64;
+            jz = (real)jz64;
+        } else {
+            T = f0 + f1 + f2 + f3 + f4 + f5 + f6;
+            jx = f1 - f2;
+            jy = f3 - f4;
+            jz = f5 - f6;
+            hjx = fma(tb[4], jz, fma(tb[3], jy, tb[0] * jx));
+            hjy = fma(tb[5], jz, fma(tb[1], jy, tb[3] * jx));
+            hjz = fma(tb[2], jz, fma(tb[5], jy, tb[4] * jx));
+        }
         T_.v[v] = T;
         X_.v[v] = hjx;
         Y_.v[v] = hjy;
@@ -372,9 +440,11 @@ __device__ __forceinline__ void collide_store(const Cell<real> &c, const real *_
                     dout = (double)G_[0].v[v] + (double)G_[1].v[v] + (double)G_[2].v[v] + (double)G_[3].v[v] +
                            (double)G_[4].v[v] + (double)G_[5].v[v] + (double)G_[6].v[v];
                 } else {
-                    dout = (double)(T * real(0.25)) + (double)gplus(T, hjx) + (double)gminus(T, hjx) +
-                           (double)gplus(T, hjy) + (double)gminus(T, hjy) + (double)gplus(T, hjz) +
-                           (double)gminus(T, hjz);
+                    const long long i = base + v;
+                    dout = (double)(T * real(0.25)) + (double)out_pop(T, hjx, i, 0, 0) +
+                           (double)out_pop(T, hjx, i, 0, 1) + (double)out_pop(T, hjy, i, 1, 0) +
+                           (double)out_pop(T, hjy, i, 1, 1) + (double)out_pop(T, hjz, i, 2, 0) +
+                           (double)out_pop(T, hjz, i, 2, 1);
                 }
                 acc.v[R_LEAK] += dout - din;
                 if (!(dT <= 1e300)) acc.v[R_NONFINITE] += 1.0;
@@ -414,8 +484,8 @@ __device__ __forceinline__ void collide_store(const Cell<real> &c, const real *_
                     Vec<real, VEC> p, m;
 #pragma unroll
                     for (int v = 0; v < VEC; v++) {
-                        p.v[v] = gplus(T_.v[v], hj.v[v]);
-                        m.v[v] = gminus(T_.v[v], hj.v[v]);
+                        p.v[v] = out_pop(T_.v[v], hj.v[v], base + v, a, 0);
+                        m.v[v] = out_pop(T_.v[v], hj.v[v], base + v, a, 1);
                     }
                     vstore<real, VEC, NS>(d + (2 * a + 1) * N + base, p);
                     vstore<real, VEC, NS>(d + (2 * a + 2) * N + base, m);
@@ -433,14 +503,282 @@ __device__ __forceinline__ void collide_store(const Cell<real> &c, const real *_
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP32 moment storage, exact populations.  Every pulled population is
+// T/8 +- jhat_a/2 of the FP32 moments of its source node; in FP64 that sum is
+// exact, and so are the seven-term T, the differences j and the wall terms.
+// The only roundings of a step are then those of the new T and jhat/2 to
+// FP32, both dithered.  (Rounding the populations to FP32, as population
+// storage must, loses T/8 wherever it is below half an ulp of jhat/2 -- near
+// the surface T = T_lin -- with the same sign over whole regions: a coherent
+// energy sink.)
+// ---------------------------------------------------------------------------
+
+template <int VEC, int MODE>
+struct PulledX {
+    // exact T(t+1) of each node; its pre-collision j in FP32 (the stored
+    // jhat is formed from it, identically in every mode) and, for the
+    // observables, exactly
+    double T[VEC];
+    float j[3][VEC];
+    typename std::conditional<MODE != 0, double, char>::type j64[3][VEC];
+    float told[VEC];           // the node's stored T(t)
+    int ph[VEC];
+    double out_hot, out_cold;
+    bool hot, cold;
+};
+
+__device__ __forceinline__ double pop_plus(float T, float z) { return (double)T * 0.125 + (double)z; }
+__device__ __forceinline__ double pop_minus(float T, float z) { return (double)T * 0.125 - (double)z; }
+
+template <int VEC, int MODE, int NT>
+__device__ __forceinline__ void pull_mom_exact(const Cell<float> &c, int xv, int y, int z, const XLink &xl,
+                                               PulledX<VEC, MODE> &P) {
+    const long long N = c.N;
+    const int nx = c.nx, ny = c.ny, nz = c.nz;
+    const int x0 = xv * VEC;
+    const long long base = ((long long)z * ny + y) * nx + x0;
+    const float *__restrict__ sT = c.src;
+    const float *__restrict__ sX = c.src + N;
+    const float *__restrict__ sY = c.src + 2 * N;
+    const float *__restrict__ sZ = c.src + 3 * N;
+    const bool ylo = (y == 0), yhi = (y == ny - 1), zlo = (z == 0), zhi = (z == nz - 1);
+    const int ym = ylo ? (c.per[1] ? ny - 1 : y) : y - 1;
+    const int yp = yhi ? (c.per[1] ? 0 : y) : y + 1;
+    const int zm = zlo ? (c.per[2] ? nz - 1 : z) : z - 1;
+    const int zp = zhi ? (c.per[2] ? 0 : z) : z + 1;
+    const bool wym = ylo && !c.per[1], wyp = yhi && !c.per[1], wzm = zlo && !c.per[2], wzp = zhi && !c.per[2];
+    constexpr bool NL = (NT & 1) != 0;
+    Vec<float, VEC> Tc = vload<float, VEC, NL>(sT + base);
+    Vec<float, VEC> Xc = vload<float, VEC, NL>(sX + base);
+    const long long rym = ((long long)z * ny + ym) * nx + x0, ryp = ((long long)z * ny + yp) * nx + x0;
+    const long long rzm = ((long long)zm * ny + y) * nx + x0, rzp = ((long long)zp * ny + y) * nx + x0;
+    Vec<float, VEC> Tym = vload<float, VEC, NL>(sT + rym), Yym = vload<float, VEC, NL>(sY + rym);
+    Vec<float, VEC> Typ = vload<float, VEC, NL>(sT + ryp), Yyp = vload<float, VEC, NL>(sY + ryp);
+    Vec<float, VEC> Tzm = vload<float, VEC, NL>(sT + rzm), Zzm = vload<float, VEC, NL>(sZ + rzm);
+    Vec<float, VEC> Tzp = vload<float, VEC, NL>(sT + rzp), Zzp = vload<float, VEC, NL>(sZ + rzp);
+    load_phase<VEC>(c.phase + base, P.ph);
+    // x: the moments of my last node feed the next lane, of my first node the previous lane
+    const int sl = min(max(xl.srcL, 0), 63), sr = min(max(xl.srcR, 0), 63);
+    const float gotLT = __shfl(Tc.v[VEC - 1], sl, 64), gotLX = __shfl(Xc.v[VEC - 1], sl, 64);
+    const float gotRT = __shfl(Tc.v[0], sr, 64), gotRX = __shfl(Xc.v[0], sr, 64);
+    double left, right;
+    if (x0 == 0) {
+        if (c.per[0]) left = xl.haveL ? pop_plus(gotLT, gotLX) : pop_plus(sT[base + nx - 1], sX[base + nx - 1]);
+        else left = (double)c.sgn[0] * pop_minus(Tc.v[0], Xc.v[0]) + (double)c.phi[0][0];
+    } else {
+        left = xl.haveL ? pop_plus(gotLT, gotLX) : pop_plus(sT[base - 1], sX[base - 1]);
+    }
+    if (x0 + VEC == nx) {
+        if (c.per[0]) right = xl.haveR ? pop_minus(gotRT, gotRX) : pop_minus(sT[base - x0], sX[base - x0]);
+        else right = (double)c.sgn[0] * pop_plus(Tc.v[VEC - 1], Xc.v[VEC - 1]) + (double)c.phi[0][1];
+    } else {
+        right = xl.haveR ? pop_minus(gotRT, gotRX) : pop_minus(sT[base + VEC], sX[base + VEC]);
+    }
+    const double s1 = (double)c.sgn[1], s2 = (double)c.sgn[2];
+    // the gradient-axis shifts +-h of a population pair cancel in T and
+    // add 2h to j
+    const float h2x = 2.0f * c.h[0], h2y = 2.0f * c.h[1], h2z = 2.0f * c.h[2];
+#pragma unroll
+    for (int v = 0; v < VEC; v++) {
+        const double p1 = (v == 0) ? left : pop_plus(Tc.v[v - 1], Xc.v[v - 1]);
+        const double p2 = (v == VEC - 1) ? right : pop_minus(Tc.v[v + 1], Xc.v[v + 1]);
+        const double p3 = wym ? s1 * pop_minus(Tym.v[v], Yym.v[v]) + (double)c.phi[1][0]
+                              : pop_plus(Tym.v[v], Yym.v[v]);
+        const double p4 = wyp ? s1 * pop_plus(Typ.v[v], Yyp.v[v]) + (double)c.phi[1][1]
+                              : pop_minus(Typ.v[v], Yyp.v[v]);
+        const double p5 = wzm ? s2 * pop_minus(Tzm.v[v], Zzm.v[v]) + (double)c.phi[2][0]
+                              : pop_plus(Tzm.v[v], Zzm.v[v]);
+        const double p6 = wzp ? s2 * pop_plus(Tzp.v[v], Zzp.v[v]) + (double)c.phi[2][1]
+                              : pop_minus(Tzp.v[v], Zzp.v[v]);
+        P.T[v] = (double)Tc.v[v] * 0.25 + p1 + p2 + p3 + p4 + p5 + p6;
+        P.j[0][v] = (float)(p1 - p2) + h2x;
+        P.j[1][v] = (float)(p3 - p4) + h2y;
+        P.j[2][v] = (float)(p5 - p6) + h2z;
+        if constexpr (MODE != 0) {
+            P.j64[0][v] = (p1 - p2) + (double)h2x;
+            P.j64[1][v] = (p3 - p4) + (double)h2y;
+            P.j64[2][v] = (p5 - p6) + (double)h2z;
+        }
+        P.told[v] = Tc.v[v];
+    }
+    if constexpr (MODE != 0) {
+        P.out_hot = P.out_cold = 0.0;
+        const int g = c.gaxis;
+        if (g == 0) {
+            P.hot = (x0 == 0);
+            P.cold = (x0 + VEC == nx);
+            P.out_hot = pop_minus(Tc.v[0], Xc.v[0]);
+            P.out_cold = pop_plus(Tc.v[VEC - 1], Xc.v[VEC - 1]);
+        } else {
+            const Vec<float, VEC> Jc = vload<float, VEC>((g == 1 ? sY : sZ) + base);
+            P.hot = (g == 1) ? ylo : zlo;
+            P.cold = (g == 1) ? yhi : zhi;
+#pragma unroll
+            for (int v = 0; v < VEC; v++) {
+                P.out_hot += pop_minus(Tc.v[v], Jc.v[v]);
+                P.out_cold += pop_plus(Tc.v[v], Jc.v[v]);
+            }
+        }
+    }
+}
+
+template <int VEC, int MODE, int NT>
+__device__ __forceinline__ void collide_store_exact(const Cell<float> &c, const float *__restrict__ tab, int xv, int y,
+                                                    int z, bool active, const PulledX<VEC, MODE> &P, Acc &acc,
+                                                    float *__restrict__ qout, float qscale) {
+    const long long N = c.N;
+    const long long base = ((long long)z * c.ny + y) * c.nx + xv * VEC;
+    Vec<float, VEC> T_, X_, Y_, Z_;
+#pragma unroll
+    for (int v = 0; v < VEC; v++) {
+        const float *tb = tab + P.ph[v] * TABW;  // half of (I - tau^-1)
+        // only T needs the dither: jhat relaxes within a few steps, and its
+        // rounding moves no energy (the exact populations sum to T anyway)
+        const float T = dither_to_float(P.T[v], (unsigned long long)(base + v));
+        const float jx = P.j[0][v], jy = P.j[1][v], jz = P.j[2][v];
+        T_.v[v] = T;
+        X_.v[v] = fmaf(tb[4], jz, fmaf(tb[3], jy, tb[0] * jx));
+        Y_.v[v] = fmaf(tb[5], jz, fmaf(tb[1], jy, tb[3] * jx));
+        Z_.v[v] = fmaf(tb[2], jz, fmaf(tb[5], jy, tb[4] * jx));
+        if constexpr (MODE != 0) {
+            if (active) {
+                const double jx64 = P.j64[0][v], jy64 = P.j64[1][v], jz64 = P.j64[2][v];
+                const double hx = fma((double)tb[4], jz64, fma((double)tb[3], jy64, (double)tb[0] * jx64));
+                const double hy = fma((double)tb[5], jz64, fma((double)tb[1], jy64, (double)tb[3] * jx64));
+                const double hz = fma((double)tb[2], jz64, fma((double)tb[5], jy64, (double)tb[4] * jx64));
+                const double qx = 0.5 * jx64 + hx, qy = 0.5 * jy64 + hy, qz = 0.5 * jz64 + hz;
+                acc.v[R_QX] += qx;
+                acc.v[R_QY] += qy;
+                acc.v[R_QZ] += qz;
+                acc.v[R_TSUM] += (double)T;
+                // the next step's populations of this node sum exactly to the
+                // stored T, so the rounding energy is that of T alone
+                acc.v[R_LEAK] += (double)T - P.T[v];
+                const double dT = fabs((double)T - (double)P.told[v]);
+                if (!(dT <= 1e300)) acc.v[R_NONFINITE] += 1.0;
+                else acc.v[R_RESID] = fmax(acc.v[R_RESID], dT);
+                if constexpr (MODE == 3) {
+                    const long long i = base + v;
+                    qout[i] = (float)(qx * (double)qscale);
+                    qout[N + i] = (float)(qy * (double)qscale);
+                    qout[2 * N + i] = (float)(qz * (double)qscale);
+                }
+            }
+        }
+    }
+    if constexpr (MODE != 0) {
+        if (active) {
+            const double hg = (double)c.h[c.gaxis];
+            const double nodes = (c.gaxis == 0) ? 1.0 : (double)VEC;
+            if (P.hot) acc.v[R_PHI_HOT] += nodes * hg - 2.0 * P.out_hot;
+            if (P.cold) acc.v[R_PHI_COLD] += 2.0 * P.out_cold + nodes * hg;
+        }
+    }
+    if constexpr (MODE <= 1) {
+        if (active) {
+            float *__restrict__ d = c.dst;
+            constexpr bool NS = (NT & 2) != 0;
+            vstore<float, VEC, NS>(d + base, T_);
+            vstore<float, VEC, NS>(d + N + base, X_);
+            vstore<float, VEC, NS>(d + 2 * N + base, Y_);
+            vstore<float, VEC, NS>(d + 3 * N + base, Z_);
+        }
+    }
+}
+
+// FP32 population storage: T, j and jhat in FP64 from the FP32 inputs, the
+// seven outputs T/4, T/8 +- jhat_a/2 formed exactly in FP64 and each
+// dithered to FP32 (these are the only roundings of the step).
+template <int VEC, int MODE, int NT>
+__device__ __forceinline__ void collide_store_pop32(const Cell<float> &c, const float *__restrict__ tab, int xv, int y,
+                                                    int z, bool active, const Pulled<float, VEC> &P, Acc &acc,
+                                                    float *__restrict__ qout, float qscale) {
+    const long long N = c.N;
+    const long long base = ((long long)z * c.ny + y) * c.nx + xv * VEC;
+    const float hx = c.h[0], hy = c.h[1], hz = c.h[2];
+    Vec<float, VEC> G[Q];
+#pragma unroll
+    for (int v = 0; v < VEC; v++) {
+        const float f0 = P.f0[v];
+        const float f1 = P.r[0][v] + hx, f2 = P.r[1][v] - hx;
+        const float f3 = P.r[2][v] + hy, f4 = P.r[3][v] - hy;
+        const float f5 = P.r[4][v] + hz, f6 = P.r[5][v] - hz;
+        const double T = (((((((double)f0 + (double)f1) + (double)f2) + (double)f3) + (double)f4) + (double)f5) +
+                          (double)f6);
+        const double jx = (double)f1 - (double)f2, jy = (double)f3 - (double)f4, jz = (double)f5 - (double)f6;
+        const float *tb = tab + P.ph[v] * TABW;  // half of (I - tau^-1)
+        const double hjx = fma((double)tb[4], jz, fma((double)tb[3], jy, (double)tb[0] * jx));
+        const double hjy = fma((double)tb[5], jz, fma((double)tb[1], jy, (double)tb[3] * jx));
+        const double hjz = fma((double)tb[2], jz, fma((double)tb[5], jy, (double)tb[4] * jx));
+        const unsigned long long key = (unsigned long long)(base + v) * 8ull;
+        G[0].v[v] = dither_to_float(T * 0.25, key);
+        G[1].v[v] = dither_to_float(fma(T, 0.125, hjx), key + 1);
+        G[2].v[v] = dither_to_float(fma(T, 0.125, -hjx), key + 2);
+        G[3].v[v] = dither_to_float(fma(T, 0.125, hjy), key + 3);
+        G[4].v[v] = dither_to_float(fma(T, 0.125, -hjy), key + 4);
+        G[5].v[v] = dither_to_float(fma(T, 0.125, hjz), key + 5);
+        G[6].v[v] = dither_to_float(fma(T, 0.125, -hjz), key + 6);
+        if constexpr (MODE != 0) {
+            if (active) {
+                // T(t+1) as the next step sums it; the rounding energy is its
+                // difference to the exact T
+                const double Tn = (double)G[0].v[v] + (double)G[1].v[v] + (double)G[2].v[v] + (double)G[3].v[v] +
+                                  (double)G[4].v[v] + (double)G[5].v[v] + (double)G[6].v[v];
+                const double qx = 0.5 * jx + hjx, qy = 0.5 * jy + hjy, qz = 0.5 * jz + hjz;
+                acc.v[R_QX] += qx;
+                acc.v[R_QY] += qy;
+                acc.v[R_QZ] += qz;
+                acc.v[R_TSUM] += Tn;
+                acc.v[R_LEAK] += Tn - T;
+                const double dT = fabs(Tn - (double)P.told[v]);
+                if (!(dT <= 1e300)) acc.v[R_NONFINITE] += 1.0;
+                else acc.v[R_RESID] = fmax(acc.v[R_RESID], dT);
+                if constexpr (MODE == 3) {
+                    const long long i = base + v;
+                    qout[i] = (float)(qx * (double)qscale);
+                    qout[N + i] = (float)(qy * (double)qscale);
+                    qout[2 * N + i] = (float)(qz * (double)qscale);
+                }
+            }
+        }
+    }
+    if constexpr (MODE != 0) {
+        if (active) {
+            const double hg = (double)c.h[c.gaxis];
+            const double nodes = (c.gaxis == 0) ? 1.0 : (double)VEC;
+            if (P.hot) acc.v[R_PHI_HOT] += nodes * hg - 2.0 * P.out_hot;
+            if (P.cold) acc.v[R_PHI_COLD] += 2.0 * P.out_cold + nodes * hg;
+        }
+    }
+    if constexpr (MODE <= 1) {
+        if (active) {
+            float *__restrict__ d = c.dst;
+            constexpr bool NS = (NT & 2) != 0;
+#pragma unroll
+            for (int i = 0; i < Q; i++) vstore<float, VEC, NS>(d + i * N + base, G[i]);
+        }
+    }
+}
+
 template <typename real, int VEC, int MODE, int NT = 0, int STORAGE = 0>
 __device__ __forceinline__ void node_update(const Cell<real> &c, const real *__restrict__ tab, int xv, int y, int z,
                                             bool active, const XLink &xl, Acc &acc, real *__restrict__ qout,
                                             real qscale) {
-    Pulled<real, VEC> P;
-    if constexpr (STORAGE == 1) pull_mom<real, VEC, MODE, NT>(c, xv, y, z, xl, P);
-    else pull_dist<real, VEC, MODE, NT>(c, xv, y, z, xl, P);
-    collide_store<real, VEC, MODE, NT, STORAGE>(c, tab, xv, y, z, active, P, acc, qout, qscale);
+    if constexpr (STORAGE == 1 && sizeof(real) == 4) {
+        PulledX<VEC, MODE> P;
+        pull_mom_exact<VEC, MODE, NT>(c, xv, y, z, xl, P);
+        collide_store_exact<VEC, MODE, NT>(c, tab, xv, y, z, active, P, acc, qout, qscale);
+    } else if constexpr (STORAGE == 0 && sizeof(real) == 4) {
+        Pulled<float, VEC> P;
+        pull_dist<float, VEC, MODE, NT>(c, xv, y, z, xl, P);
+        collide_store_pop32<VEC, MODE, NT>(c, tab, xv, y, z, active, P, acc, qout, qscale);
+    } else {
+        Pulled<real, VEC> P;
+        if constexpr (STORAGE == 1) pull_mom<real, VEC, MODE, NT>(c, xv, y, z, xl, P);
+        else pull_dist<real, VEC, MODE, NT>(c, xv, y, z, xl, P);
+        collide_store<real, VEC, MODE, NT, STORAGE>(c, tab, xv, y, z, active, P, acc, qout, qscale);
+    }
 }
 
 template <typename real>

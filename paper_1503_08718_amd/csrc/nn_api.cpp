@@ -19,6 +19,7 @@ static mrtlbm_status ret(hipError_t e, const char *what) { return e == hipSucces
 static bool geom(int n, int d, int h, int w, int cin, int cout, int circ, ConvGeom *g) {
     if (n < 1 || d < 1 || h < 1 || w < 1 || cin < 8 || cin % 8 || cout < 16 || cout % 16 || circ < 0 || circ > 7)
         return false;
+    if ((long long)n * d * h * w >= (1LL << 31)) return false;  // voxel indices are 32-bit in the kernels
     g->n = n; g->D = d; g->H = h; g->W = w;
     g->cin = cin; g->cout = cout;
     g->kpad = mrtlbm_nn_kpad(cin);

@@ -24,20 +24,32 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 
 
-// neighbour voxel of v (flattened over n, z, y, x) at tap offset; -1 if it
-// falls into zero padding
-__device__ __forceinline__ long long neighbour(const ConvGeom &g, long long v, int tap) {
-    const int x = (int)(v % g.W);
-    long long r = v / g.W;
-    const int y = (int)(r % g.H);
-    r /= g.H;
-    const int z = (int)(r % g.D);
-    const long long nb = r / g.D;
-    int px = x + tap % 3 - 1, py = y + (tap / 3) % 3 - 1, pz = z + tap / 9 - 1;
-    if (px < 0 || px >= g.W) { if (!(g.circ & 1)) return -1; px = (px + g.W) % g.W; }
-    if (py < 0 || py >= g.H) { if (!(g.circ & 2)) return -1; py = (py + g.H) % g.H; }
-    if (pz < 0 || pz >= g.D) { if (!(g.circ & 4)) return -1; pz = (pz + g.D) % g.D; }
-    return ((nb * g.D + pz) * g.H + py) * g.W + px;
+// coordinates of voxel v (flattened over n, z, y, x; fewer than 2^31 voxels,
+// checked on the host), computed once per voxel with 32-bit arithmetic
+struct VoxPos {
+    int x, y, z, nb;
+};
+
+__device__ __forceinline__ VoxPos vox_pos(const ConvGeom &g, int v) {
+    const unsigned u = (unsigned)v;
+    const unsigned r = u / (unsigned)g.W;
+    const unsigned r2 = r / (unsigned)g.H;
+    VoxPos p;
+    p.x = (int)(u - r * (unsigned)g.W);
+    p.y = (int)(r - r2 * (unsigned)g.H);
+    p.nb = (int)(r2 / (unsigned)g.D);
+    p.z = (int)(r2 - (unsigned)p.nb * (unsigned)g.D);
+    return p;
+}
+
+// neighbour of a voxel at tap offset ((tap / 9, tap / 3 % 3, tap % 3) - 1);
+// -1 if it falls into zero padding
+__device__ __forceinline__ int neighbour_at(const ConvGeom &g, const VoxPos &p, int tap) {
+    int px = p.x + tap % 3 - 1, py = p.y + (tap / 3) % 3 - 1, pz = p.z + tap / 9 - 1;
+    if (px < 0 || px >= g.W) { if (!(g.circ & 1)) return -1; px = px < 0 ? px + g.W : px - g.W; }
+    if (py < 0 || py >= g.H) { if (!(g.circ & 2)) return -1; py = py < 0 ? py + g.H : py - g.H; }
+    if (pz < 0 || pz >= g.D) { if (!(g.circ & 4)) return -1; pz = pz < 0 ? pz + g.D : pz - g.D; }
+    return ((p.nb * g.D + pz) * g.H + py) * g.W + px;
 }
 
 __device__ __forceinline__ bf16x8 zero8() {
@@ -61,11 +73,11 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const bf16 *__restrict__ in, c
     for (int i = 0; i < MT; i++)
 #pragma unroll
         for (int j = 0; j < NT; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    long long vrow[MT];
+    VoxPos vrow[MT];
 #pragma unroll
     for (int i = 0; i < MT; i++) {
         const long long v = v0 + i * 16 + (lane & 15);
-        vrow[i] = v < nvox ? v : nvox - 1;
+        vrow[i] = vox_pos(g, (int)(v < nvox ? v : nvox - 1));
     }
     const int kq = (lane >> 4) * 8;  // this lane's first k inside a 32-wide chunk
     const int K27 = 27 * g.cin;
@@ -75,8 +87,8 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const bf16 *__restrict__ in, c
         const int tap = k / g.cin, c0 = k - tap * g.cin;
 #pragma unroll
         for (int i = 0; i < MT; i++) {
-            long long p = (k < K27) ? neighbour(g, vrow[i], tap) : -1;
-            a[i] = (p >= 0) ? *reinterpret_cast<const bf16x8 *>(in + p * g.cin + c0) : zero8();
+            const int p = (k < K27) ? neighbour_at(g, vrow[i], tap) : -1;
+            a[i] = (p >= 0) ? *reinterpret_cast<const bf16x8 *>(in + (long long)p * g.cin + c0) : zero8();
         }
 #pragma unroll
         for (int j = 0; j < NT; j++) {
@@ -150,17 +162,19 @@ __global__ void __launch_bounds__(64) k_conv_wgrad(const bf16 *__restrict__ x, c
             a[e] = (v < ve) ? dy[v * g.cout + co] : (bf16)0.0f;
         }
 #pragma unroll
-        for (int j = 0; j < 2; j++)
+        for (int e = 0; e < 8; e++) {
+            const long long v = vq + e;
+            const VoxPos pos = vox_pos(g, (int)(v < ve ? v : vb));
 #pragma unroll
-            for (int e = 0; e < 8; e++) {
-                const long long v = vq + e;
+            for (int j = 0; j < 2; j++) {
                 bf16 val = (bf16)0.0f;
                 if (v < ve && kcol[j] < K27) {
-                    const long long p = neighbour(g, v, tap[j]);
-                    if (p >= 0) val = x[p * g.cin + ci[j]];
+                    const int p = neighbour_at(g, pos, tap[j]);
+                    if (p >= 0) val = x[(long long)p * g.cin + ci[j]];
                 }
                 b[j][e] = val;
             }
+        }
 #pragma unroll
         for (int j = 0; j < 2; j++) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[j], 0, 0, 0);
     }

@@ -305,7 +305,10 @@ def test_max_steps_gives_partial_result(Medium):
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("case", CASES[:5] + [(32, 16, 12, 5, 2, (PERIODIC, ADIABATIC, 0), 9)],
                          ids=lambda c: "x".join(map(str, c[:3])) + f"_g{c[4]}")
-def test_moment_storage_bitwise_equals_populations(Medium, case, prec):
+def test_moment_storage_equals_populations(Medium, case, prec):
+    """FP64: bit for bit.  FP32: the moment path keeps the populations exact
+    and the population path must round them (dithered), so the two agree to
+    the FP32 noise of the fields."""
     import torch
 
     nx, ny, nz, nph, grad, sides, seed = case
@@ -321,9 +324,16 @@ def test_moment_storage_bitwise_equals_populations(Medium, case, prec):
         g.step(37)
         runs.append((g.temperature(), g.flux(), g.keff(), g.solve(1e-30, "keff", 137, check_every=50)))
     (ta, qa, ka, ra), (tb, qb, kb, rb) = runs
-    assert torch.equal(ta, tb)
-    assert torch.equal(qa, qb)
-    assert ka == kb and ra == rb
+    if prec == "f64":
+        assert torch.equal(ta, tb)
+        assert torch.equal(qa, qb)
+        assert ka == kb and ra == rb
+        return
+    assert (ta - tb).abs().max().item() <= 1e-5 * max(1.0, ta.abs().max().item())
+    assert (qa - qb).abs().max().item() <= 1e-5 * max(1e-3, qa.abs().max().item())
+    for a, b in ((ka, kb), (ra, rb)):
+        for key in ("keff_hot", "keff_cold", "keff_vol"):
+            assert abs(a[key] - b[key]) <= 1e-4 * max(1.0, abs(b[key])), key
 
 
 def test_moment_storage_matches_oracle_and_resumes(Medium):
@@ -357,8 +367,10 @@ def test_moment_storage_batch(Medium):
     ra, _ = batch_solve(a, tol=1e-30, kind="keff", max_steps=400, check_every=100)
     rb, _ = batch_solve(b, tol=1e-30, kind="keff", max_steps=400, check_every=100)
     for x, y, p, q in zip(a, b, ra, rb):
-        assert torch.equal(x.temperature(), y.temperature())
-        assert p == q
+        # FP32: exact populations (moments) vs dithered ones (populations)
+        assert (x.temperature() - y.temperature()).abs().max().item() < 1e-5
+        for key in ("keff_hot", "keff_cold", "keff_vol"):  # early transient: k_cold is still ~1e-3
+            assert abs(p[key] - q[key]) <= 1e-4 * abs(q[key]) + 1e-6, key
 
 
 # ---------------------------------------------------------------------------
