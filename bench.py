@@ -55,7 +55,10 @@ def bytes_per_update(prec: str, storage: str) -> float:
 # reading for a plain 1 GiB copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000);
 # keyed by workload, storage and launch shape (vec, bx, by, nt, map).  Drop an
 # entry whenever its kernel changes.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    ("braid256_f32", "moments", (4, 64, 4, 2, 1)): 563_211_354,
+    ("braid256_f32", "populations", (4, 64, 2, 3, 0)): 956_410_227,
+}
 
 
 def parse():
