@@ -120,9 +120,17 @@ def cpu_baseline(m, sample_steps):
     o.step(steps)
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    # and on one thread, over a few seconds' worth of steps
+    o.set_threads(1)
+    s1 = max(1, int(round(1.2e8 / n)))
+    t0 = time.perf_counter()
+    o.step(s1)
+    dt1 = time.perf_counter() - t0
     return {"value": round(n * steps / dt / 1e6, 2), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "single_thread_value": round(n * s1 / dt1 / 1e6, 2),
             "sample": f"{steps} FP64 oracle steps on the same {m.nx}x{m.ny}x{m.nz} braided cell "
-                      f"(x gradient, periodic sides), OpenMP over z-planes"}
+                      f"(x gradient, periodic sides), OpenMP over z-planes; {s1} more steps on one thread "
+                      f"for single_thread_value"}
 
 
 def mode_throughput(args):
