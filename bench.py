@@ -126,8 +126,14 @@ def cpu_baseline(m, sample_steps):
     t0 = time.perf_counter()
     o.step(s1)
     dt1 = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": round(n * steps / dt / 1e6, 2), "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "single_thread_value": round(n * s1 / dt1 / 1e6, 2),
+            "single_thread_value": round(n * s1 / dt1 / 1e6, 2), "cpu_model": model,
             "sample": f"{steps} FP64 oracle steps on the same {m.nx}x{m.ny}x{m.nz} braided cell "
                       f"(x gradient, periodic sides), OpenMP over z-planes; {s1} more steps on one thread "
                       f"for single_thread_value"}
