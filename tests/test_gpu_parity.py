@@ -209,6 +209,27 @@ def test_fp32_converges_past_its_rounding_floor(Medium):
     assert abs(r64["keff_leak"]) < 1e-10 * r64["keff"]
 
 
+@pytest.mark.parametrize("storage", ["moments", "populations"])
+def test_fp32_has_no_rounding_floor(Medium, storage):
+    """Adiabatic sides, where round-to-nearest FP32 lost energy coherently
+    (T/8 absorbed by jhat/2 in the populations) and stalled at a fixed point:
+    with exact population rebuild (moments) or dithered populations, and a
+    dithered T, the FP32 solve lands on the FP64 answer far inside the
+    tolerance and its rounding energy is noise."""
+    m = w.braid(64, 64, 64, 30.0, 0.5)
+    sides = ("periodic", "adiabatic", "adiabatic")
+    g64 = Medium(m.phase, m.k, precision="f64").set_bc(0, 1.0, 0.0, sides).init()
+    r64 = g64.solve(1e-9, "keff", 4_000_000, check_every=1000)
+    g32 = Medium(m.phase, m.k, precision="f32", storage=storage).set_bc(0, 1.0, 0.0, sides).init()
+    r32 = g32.solve(1e-6, "keff", 4_000_000, check_every=1000)
+    assert r64["converged"] and r32["converged"], (r64, r32)
+    assert rel(r32["keff"], r64["keff"]) < 2e-6, (r32, r64)
+    assert rel(r32["keff_vol"], r64["keff_vol"]) < 2e-6
+    # one step's rounding energy: random, ~sqrt(N) dithered roundings
+    # (round-to-nearest left a coherent 5e-5 here)
+    assert abs(r32["keff_leak"]) < 1e-5 * r32["keff"]
+
+
 # ---------------------------------------------------------------------------
 # full-size windows: the configurations the benchmark times
 # ---------------------------------------------------------------------------
