@@ -20,6 +20,9 @@ Other modes (each prints one JSON line):
                     learned warm start: steps and cells per hour
   --mode paper      the paper's unit cell (Eqs. 32-37) over braiding angle
                     and fibre fraction: k_T, k_L, trends, periodic vs adiabatic
+  --mode network    the warm-start network's BF16 matrix-core work: one
+                    inference and one training iteration, TFLOP/s and
+                    fraction of the dense BF16 peak
 """
 
 from __future__ import annotations
@@ -35,6 +38,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix-core peak
 TUNE_CACHE = os.path.join(ROOT, "paper_1503_08718_amd", "tuned_launch.txt")
 WORKLOADS = {
     # name: (n, precision)
@@ -67,7 +71,7 @@ def parse():
     p.add_argument("--steps", type=int, default=4000)
     p.add_argument("--warmup", type=int, default=400)
     p.add_argument("--mode", default="throughput",
-                   choices=["throughput", "copy", "solve", "sweep", "warmstart", "paper"])
+                   choices=["throughput", "copy", "solve", "sweep", "warmstart", "paper", "network"])
     p.add_argument("--workload", default="braid256_f32", choices=sorted(WORKLOADS))
     p.add_argument("--check-every", type=int, default=200)
     p.add_argument("--storage", default="moments", choices=sorted(STORAGE_VALUES))
@@ -225,6 +229,59 @@ def mode_copy(args):
     dt = (time.perf_counter() - t0) / reps
     return {"mode": "copy", "bytes_read_per_copy": 4 * n, "bytes_written_per_copy": 4 * n, "copies": reps + 3,
             "GB_s": round(8 * n / dt / 1e9, 1)}
+
+
+def mode_network(args):
+    """The warm-start network on its 64^3 grid with seeded random weights and
+    inputs: one inference (forward at batch 1 and 4) and one training
+    iteration (forward, loss, input and weight gradients, Adam; batch 4),
+    each timed with HIP events on the network's stream over repeated
+    passes.  FLOPs are the algorithmic 2 * voxels * 27 * C_in * C_out per
+    convolution pass."""
+    import torch
+
+    from paper_1503_08718_amd import warmstart as ws
+
+    def timed(fn, reps):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def train_iter(net):
+        net.forward()
+        net.loss_and_grad()
+        net.backward()
+        net.adam()
+
+    out = {"mode": "network", "grid": 64, "layers": len(ws.LAYERS), "peak_TFLOP_s": BF16_PEAK_TFLOPS,
+           "data": "seeded random weights and inputs"}
+    g = torch.Generator().manual_seed(args.seed)
+    for batch in (1, 4):
+        net = ws.Net(n=64, batch=batch, seed=0)
+        net.act["x"].copy_(torch.rand(net.act["x"].shape, generator=g).to(torch.bfloat16))
+        net.target.copy_(torch.rand(net.target.shape, generator=g) * 0.1)
+        rec = {"batch": batch}
+        ms = timed(net.forward, 20)
+        f = ws.forward_flops(net)
+        rec["forward"] = {"ms": round(ms, 4), "GFLOP": round(f / 1e9, 3), "TFLOP_s": round(f / ms / 1e9, 2),
+                          "frac": round(f / ms / 1e9 / BF16_PEAK_TFLOPS, 4)}
+        if batch == 4:
+            ms = timed(lambda: train_iter(net), 10)
+            f = ws.iteration_flops(net)
+            rec["train_iteration"] = {"ms": round(ms, 4), "GFLOP": round(f / 1e9, 3),
+                                      "TFLOP_s": round(f / ms / 1e9, 2),
+                                      "frac": round(f / ms / 1e9 / BF16_PEAK_TFLOPS, 4)}
+        out[f"batch{batch}"] = rec
+        print(f"network batch {batch} done", file=sys.stderr, flush=True)
+        del net
+    return out
 
 
 def _solve(m, prec, axis, sides, tol, args, T0=None, flux=False, start="zero", net=None, canonical=False):
@@ -475,6 +532,8 @@ def main():
         line = mode_sweep(args)
     elif args.mode == "paper":
         line = mode_paper(args)
+    elif args.mode == "network":
+        line = mode_network(args)
     else:
         from paper_1503_08718_amd import warmstart
 

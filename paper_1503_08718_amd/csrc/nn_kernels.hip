@@ -206,15 +206,36 @@ __global__ void k_sum_rows(const float *__restrict__ p, int rows, float scale, f
     }
 }
 
-// bias gradient partials: partials[s][c] = sum over the split's voxels of dy[v][c]
-__global__ void k_bias_grad(const bf16 *__restrict__ dy, long long nvox, int c, long long vox_per_split,
-                            float *__restrict__ partials) {
-    const int s = blockIdx.x;
+// bias gradient partials: partials[s][c] = sum over the split's voxels of dy[v][c].
+// With c <= BIAS_THREADS the block's threads form BIAS_THREADS / c voxel lanes
+// (thread t: channel t % c, lane t / c), so a wave reads whole voxel rows;
+// lane l sums voxels vb + l, vb + l + lanes, ..., and the lanes' sums are
+// added in lane order.  Wider layers keep one thread per channel.
+constexpr int BIAS_THREADS = 256;
+
+__global__ void __launch_bounds__(BIAS_THREADS)
+k_bias_grad(const bf16 *__restrict__ dy, long long nvox, int c, long long vox_per_split, float *__restrict__ partials) {
+    __shared__ float red[BIAS_THREADS];
+    const int s = blockIdx.x, t = threadIdx.x;
     const long long vb = s * vox_per_split, ve = min(nvox, vb + vox_per_split);
-    for (int ch = threadIdx.x; ch < c; ch += blockDim.x) {
-        float acc = 0.0f;
-        for (long long v = vb; v < ve; v++) acc += (float)dy[v * c + ch];
-        partials[(long long)s * c + ch] = acc;
+    if (c > BIAS_THREADS) {
+        for (int ch = t; ch < c; ch += BIAS_THREADS) {
+            float acc = 0.0f;
+            for (long long v = vb; v < ve; v++) acc += (float)dy[v * c + ch];
+            partials[(long long)s * c + ch] = acc;
+        }
+        return;
+    }
+    const int lanes = BIAS_THREADS / c, ch = t % c, lane = t / c;
+    float acc = 0.0f;
+    if (lane < lanes)
+        for (long long v = vb + lane; v < ve; v += lanes) acc += (float)dy[v * c + ch];
+    red[t] = acc;
+    __syncthreads();
+    if (t < c) {
+        float sum = 0.0f;
+        for (int l = 0; l < lanes; l++) sum += red[l * c + t];
+        partials[(long long)s * c + t] = sum;
     }
 }
 
@@ -503,7 +524,7 @@ hipError_t nn_conv_wgrad(const void *x, const void *dy, const ConvGeom &g, int s
 
 hipError_t nn_bias_grad(const void *dy, long long nvox, int c, int splits, float *partials, float *db, hipStream_t s) {
     long long per = (nvox + splits - 1) / splits;
-    hipLaunchKernelGGL(k_bias_grad, dim3(splits), dim3(128), 0, s, (const bf16 *)dy, nvox, c, per, partials);
+    hipLaunchKernelGGL(k_bias_grad, dim3(splits), dim3(BIAS_THREADS), 0, s, (const bf16 *)dy, nvox, c, per, partials);
     hipLaunchKernelGGL(k_sum_splits, dim3(1), dim3(256), 0, s, partials, (long long)c, splits, db);
     return hipGetLastError();
 }

@@ -400,17 +400,26 @@ def make_dataset(media, size=64, tol=1e-5, chunk=128, log=print):
         seconds=time.perf_counter() - t0, mean_steps=float(np.mean(steps)))
 
 
+# resolution level of each convolution (grid n >> level)
+LEVEL = {"c00": 0, "c01": 0, "c10": 1, "c11": 1, "c20": 2, "c21": 2, "c30": 3, "c31": 3, "c22": 2, "c23": 2,
+         "c12": 1, "c13": 1, "c02": 0, "c03": 0, "c04": 0}
+
+
+def layer_flops(net: Net) -> dict:
+    """Algorithmic FLOPs of each convolution's forward pass:
+    2 * voxels * 27 * C_in * C_out (the K padding of the MFMA tiles not counted)."""
+    return {name: 2.0 * net.batch * (net.n >> LEVEL[name]) ** 3 * 27 * cin * cout for name, cin, cout, _ in LAYERS}
+
+
+def forward_flops(net: Net) -> float:
+    """Matrix-core FLOPs of one forward pass (inference)."""
+    return sum(layer_flops(net).values())
+
+
 def iteration_flops(net: Net) -> float:
     """Matrix-core FLOPs of one training iteration (forward, input and weight
     gradients; the first layer has no input gradient)."""
-    level = {"c00": 0, "c01": 0, "c10": 1, "c11": 1, "c20": 2, "c21": 2, "c30": 3, "c31": 3, "c22": 2, "c23": 2,
-             "c12": 1, "c13": 1, "c02": 0, "c03": 0, "c04": 0}
-    tot = 0.0
-    for name, cin, cout, _ in LAYERS:
-        vox = net.batch * (net.n >> level[name]) ** 3
-        f = 2.0 * vox * 27 * cin * cout
-        tot += f * (2 if name == "c00" else 3)
-    return tot
+    return sum(f * (2 if name == "c00" else 3) for name, f in layer_flops(net).items())
 
 
 def train(net: Net, data, iters=2000, lr=1e-3, seed=0, log=print, log_every=100):
