@@ -80,3 +80,55 @@ def test_product_does_not_touch_the_oracle():
             if fn.endswith((".py", ".cpp", ".hip", ".h")):
                 txt = open(os.path.join(dirpath, fn)).read()
                 assert "oracle" not in txt.lower(), fn
+
+
+def _c_kind(decl: str) -> str:
+    """Argument class of one C parameter (type and name) or return type."""
+    words = decl.replace("*", " * ").replace("[", " [ ").replace("const", " ").split()
+    if "*" in words or "[" in words or words[0] == "mrtlbm_progress_fn":
+        return "ptr"
+    kinds = {("long", "long"): "ll", ("double",): "double", ("float",): "float", ("size_t",): "size",
+             ("int",): "int", ("mrtlbm_precision",): "int", ("mrtlbm_tol_kind",): "int",
+             ("mrtlbm_status",): "int", ("void",): "void"}
+    for n in (2, 1):
+        if tuple(words[:n]) in kinds:
+            return kinds[tuple(words[:n])]
+    raise AssertionError(f"unknown C type in {decl!r}")
+
+
+def _py_kind(t) -> str:
+    if t is None:
+        return "void"
+    if t in (ctypes.c_void_p, ctypes.c_char_p) or hasattr(t, "_type_") and isinstance(t._type_, type) \
+            or getattr(t, "_flags_", 0) & 1:  # POINTER(...) or CFUNCTYPE(...)
+        return "ptr"
+    return {ctypes.c_double: "double", ctypes.c_float: "float", ctypes.c_int: "int", ctypes.c_longlong: "ll",
+            ctypes.c_size_t: "size"}[t]
+
+
+def test_binding_signatures_match_the_headers(lib):
+    # every declared function: same arity and argument classes in the ctypes binding
+    import re
+
+    decls = {}
+    inc = os.path.join(ROOT, "include")
+    for fn in sorted(os.listdir(inc)):
+        if not fn.endswith(".h"):
+            continue
+        txt = open(os.path.join(inc, fn)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        txt = re.sub(r"//[^\n]*", "", txt)
+        txt = "\n".join(l for l in txt.splitlines() if not l.lstrip().startswith("#"))
+        for m in re.finditer(r"([A-Za-z_][\w\s\*]*?)\b(mrtlbm_[a-z0-9_]+)\s*\(([^;{]*?)\)\s*;", txt, flags=re.S):
+            ret, name, params = m.group(1), m.group(2), " ".join(m.group(3).split())
+            ret = ret.split("\n")[-1].strip() or ret.strip()
+            if "typedef" in ret:
+                continue
+            args = [] if params in ("", "void") else [_c_kind(p) for p in params.split(",")]
+            decls[name] = (_c_kind(ret.replace("extern", "").replace('"C"', "").strip()), args)
+    assert len(decls) == len(pkg.declared_symbols()), sorted(set(pkg.declared_symbols()) - set(decls))
+    for name, (ret, args) in decls.items():
+        f = getattr(lib, name)
+        got = [_py_kind(a) for a in (f.argtypes or [])]
+        assert got == args, (name, got, args)
+        assert _py_kind(f.restype) == ret, (name, f.restype, ret)
