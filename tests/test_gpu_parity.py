@@ -230,6 +230,42 @@ def test_fp32_has_no_rounding_floor(Medium, storage):
     assert abs(r32["keff_leak"]) < 1e-5 * r32["keff"]
 
 
+# extents of 1 and 2: a node is its own periodic neighbour, or sits on both
+# walls of an axis at once
+DEGENERATE = [
+    (1, 5, 4, 0, (0, PERIODIC, ADIABATIC)),
+    (5, 1, 3, 1, (ADIABATIC, 0, PERIODIC)),
+    (4, 3, 1, 2, (PERIODIC, ADIABATIC, 0)),
+    (2, 2, 2, 0, (0, ADIABATIC, ADIABATIC)),
+    (1, 1, 1, 0, (0, PERIODIC, PERIODIC)),
+    (8, 1, 1, 0, (0, PERIODIC, ADIABATIC)),
+]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("storage", ["populations", "moments"])
+@pytest.mark.parametrize("case", DEGENERATE, ids=lambda c: "x".join(map(str, c[:3])) + f"_g{c[3]}")
+def test_degenerate_extents(Medium, case, storage, prec):
+    nx, ny, nz, grad, sides = case
+    m = w.random_medium(11, nx, ny, nz, 2)
+    T0 = np.random.default_rng(11).uniform(-0.5, 1.5, m.phase.shape)
+    g = Medium(m.phase, m.k, precision=prec, storage=storage)
+    g.set_bc(grad, 0.8, -0.4, [SIDE_NAMES[s] for s in sides]).init(T0)
+    o = Oracle(m.phase, m.k)
+    o.set_bc(grad, 0.8, -0.4, sides)
+    o.init(T0)
+    tol = 1e-12 if prec == "f64" else 1e-5
+    for n in (1, 40):
+        g.step(n)
+        o.step(n)
+        assert field_err(g, o) < tol, n
+    kg = g.keff()
+    o.step(1)
+    ko = o.keff()
+    for key in ("keff_hot", "keff_cold", "keff_vol"):
+        assert abs(kg[key] - ko[key]) < (1e-10 if prec == "f64" else 2e-3) * max(1.0, abs(ko[key])), key
+
+
 # ---------------------------------------------------------------------------
 # full-size windows: the configurations the benchmark times
 # ---------------------------------------------------------------------------
