@@ -115,3 +115,33 @@ def test_xcd_tile_order_and_batch_autotune(api, storage):
     assert all(r["steps"] == 600 for r in res)
     for b, a in zip(batch, alone):
         assert torch.equal(b.state_get(), a.state_get())
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batch_of_degenerate_cells(api, prec):
+    # extents of 1 and 2 in one batch (one row per thread for nx = 1)
+    import torch
+
+    specs = [((1, 5, 4), 0, ("periodic", "periodic", "adiabatic")),
+             ((5, 1, 3), 1, ("adiabatic", "periodic", "periodic")),
+             ((4, 3, 1), 2, ("periodic", "adiabatic", "periodic")),
+             ((2, 2, 2), 0, ("periodic", "adiabatic", "adiabatic")),
+             ((1, 1, 1), 0, ("periodic", "periodic", "periodic")),
+             ((8, 1, 1), 0, ("periodic", "periodic", "adiabatic"))]
+
+    def make():
+        out = []
+        for i, (shape, g, sides) in enumerate(specs):
+            m = w.random_medium(20 + i, *shape, 2)
+            out.append(api.Medium(m.phase, m.k, precision=prec).set_bc(g, 1.0, 0.0, sides).init())
+        return out
+
+    batch, alone = make(), make()
+    res, st = api.batch_solve(batch, tol=1e-30, kind="keff", max_steps=300, check_every=100)
+    assert st == "NOT_CONVERGED"
+    for b, a, r in zip(batch, alone, res):
+        ra = a.solve(1e-30, "keff", 300, check_every=100)
+        assert r["steps"] == ra["steps"] == 300
+        assert torch.equal(b.state_get(), a.state_get())
+        for key in ("keff_hot", "keff_cold", "keff_vol"):
+            assert abs(r[key] - ra[key]) <= 1e-12 * max(1.0, abs(ra[key])), key
