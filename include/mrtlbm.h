@@ -109,7 +109,10 @@ typedef struct { int vec, bx, by, nt, map; } mrtlbm_launch;
 
 /* Bytes of caller-owned device workspace a medium of these sizes needs
  * (two state buffers of 7 reals per node, reduction partials and tables),
- * or 0 for invalid sizes.  Enough for either state storage. */
+ * or 0 for invalid sizes.  Enough for either state storage.  Valid sizes:
+ * nx, ny, nz >= 1 (an extent of 1 is allowed: the node is then its own
+ * periodic neighbour, or lies on both walls of that axis), nz <= 65535,
+ * ny <= 16 * 65535, 1 <= nphase <= 256. */
 size_t mrtlbm_workspace_bytes(int nx, int ny, int nz, int nphase, mrtlbm_precision p);
 
 /* The same for one state storage (0: 7 populations per node, 1: 4 moments
