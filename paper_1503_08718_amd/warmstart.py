@@ -289,7 +289,8 @@ class Net:
 def _gen_braid(spec):
     import workloads
 
-    m = workloads.braid(spec["nx"], spec["ny"], spec["nz"], spec["gamma"], spec["v"])
+    # one thread per worker process: the pool already spreads the cells
+    m = workloads.braid(spec["nx"], spec["ny"], spec["nz"], spec["gamma"], spec["v"], workers=1)
     return m.phase, m.k
 
 

@@ -92,3 +92,12 @@ def test_permuted_medium_roundtrip():
     K = w.full3(m.k[1])
     Kp = w.full3(p.k[1])
     assert math.isclose(Kp[0, 0], K[1, 1]) and math.isclose(Kp[0, 2], K[1, 0])
+
+
+def test_braid_voxelisation_independent_of_threads_and_slabs():
+    from workloads.media import _braid_radius
+
+    r1, f1 = _braid_radius(20, 12, 18, 33.0, z_chunk=18, workers=1)
+    for chunk, workers in ((1, 4), (5, 3), (7, 16)):
+        r, f = _braid_radius(20, 12, 18, 33.0, z_chunk=chunk, workers=workers)
+        assert np.array_equal(r, r1) and np.array_equal(f, f1), (chunk, workers)

@@ -2,7 +2,8 @@
 (braiding angle 30 deg, yarn fraction 0.5) in FP32, with the launch shape
 the benchmark loads from the autotune cache, against the FP64 oracle.
 
-Collected last: the cell takes the longest to build of all GPU tests."""
+Collected last: with the FP64 oracle on the whole cell it is the longest
+of the GPU tests."""
 
 import os
 
