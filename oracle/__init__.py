@@ -64,6 +64,7 @@ def lib():
         L.oracle_set_side_flux.restype = I
         L.oracle_set_side_flux.argtypes = [P, I, D, D]
         L.oracle_init.argtypes = [P, dp]
+        L.oracle_init_flux.argtypes = [P, dp]
         L.oracle_collide_node.argtypes = [P, I, dp, dp]
         L.oracle_step.argtypes = [P, LL]
         L.oracle_temperature.argtypes = [P, dp]
@@ -143,13 +144,20 @@ class Oracle:
         if lib().oracle_set_side_flux(self._h, int(axis), float(q_lo), float(q_hi)):
             raise ValueError("side flux needs an adiabatic axis")
 
-    def init(self, T0=None):
+    def init(self, T0=None, flux: bool = False):
+        """Equilibrium start at T0 (zero field if None); with flux=True the
+        pre-collision flux -eps tau grad T0 of Eq. 15 is added, grad T0 by
+        central differences (see oracle_init_flux)."""
         if T0 is None:
+            assert not flux, "a flux start needs a field"
             lib().oracle_init(self._h, None)
         else:
             t = np.ascontiguousarray(T0, dtype=np.float64).reshape(-1)
             assert t.size == self.n
-            lib().oracle_init(self._h, _dp(t))
+            if flux:
+                lib().oracle_init_flux(self._h, _dp(t))
+            else:
+                lib().oracle_init(self._h, _dp(t))
 
     def collide_node(self, p: int, f7) -> np.ndarray:
         fin = np.ascontiguousarray(f7, dtype=np.float64)

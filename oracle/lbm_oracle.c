@@ -301,6 +301,48 @@ void oracle_init(oracle_ctx *c, const double *T0) {
     c->steps = 0; c->phi_hot = c->phi_cold = 0.0; c->resid = 0.0;
 }
 
+/*
+ * A start that is not at equilibrium: f(x, 0) = f_eq(T0(x)) + e_i . j(x) / 2,
+ * the pre-collision flux j read backwards from Eq. 15, j = -epsilon tau grad T0
+ * (so that Eq. 15 applied to this state returns grad T0).  The higher moments
+ * of Eq. 11 stay at their equilibria.  grad T0 is estimated by central
+ * differences over two lattice spacings; at an isothermal wall the wall
+ * temperature stands half a spacing beyond the node (the half-way wall of
+ * Eq. 23), so that difference spans 1.5 spacings (1 when the axis has a
+ * single node); at an adiabatic face the missing neighbour is the node's
+ * mirror image, which carries its own value; a periodic axis wraps (Eq. 25).
+ */
+void oracle_init_flux(oracle_ctx *c, const double *T0) {
+    const int dims[3] = {c->nx, c->ny, c->nz};
+    const long long stride[3] = {1, c->nx, (long long)c->nx * c->ny};
+    for (long long x = 0; x < c->n; x++) {
+        const int pos[3] = {(int)(x % c->nx), (int)((x / c->nx) % c->ny), (int)(x / ((long long)c->nx * c->ny))};
+        double grad[3];
+        for (int a = 0; a < 3; a++) {
+            double lo, hi, span = 2.0;
+            if (pos[a] > 0) lo = T0[x - stride[a]];
+            else if (c->side[a] == SIDE_PERIODIC) lo = T0[x + (long long)(dims[a] - 1) * stride[a]];
+            else if (c->side[a] == SIDE_DIRICHLET) { lo = c->t_hot; span -= 0.5; }
+            else lo = T0[x];
+            if (pos[a] < dims[a] - 1) hi = T0[x + stride[a]];
+            else if (c->side[a] == SIDE_PERIODIC) hi = T0[x - (long long)(dims[a] - 1) * stride[a]];
+            else if (c->side[a] == SIDE_DIRICHLET) { hi = c->t_cold; span -= 0.5; }
+            else hi = T0[x];
+            grad[a] = (hi - lo) / span;
+        }
+        const double *tau = c->tau + 9 * c->phase[x];
+        double e[Q];
+        feq(T0[x], e);
+        for (int i = 0; i < Q; i++) c->f[i * c->n + x] = e[i];
+        for (int a = 0; a < 3; a++) {
+            const double j = -EPS * (tau[3 * a + 0] * grad[0] + tau[3 * a + 1] * grad[1] + tau[3 * a + 2] * grad[2]);
+            c->f[(2 * a + 1) * c->n + x] += 0.5 * j;
+            c->f[(2 * a + 2) * c->n + x] -= 0.5 * j;
+        }
+    }
+    c->steps = 0; c->phi_hot = c->phi_cold = 0.0; c->resid = 0.0;
+}
+
 /* One node's collision, Eq. 5's right-hand side: f - Omega (f - f_eq). */
 void oracle_collide_node(const oracle_ctx *c, int p, const double *fin, double *fout) {
     double T = 0.0, e[Q];

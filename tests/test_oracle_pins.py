@@ -478,3 +478,164 @@ def test_nonfinite_state_is_reported():
     o.set_f(f)
     with pytest.raises(FloatingPointError):
         o.solve(1e-12, TOL_MAXDT, 100)
+
+
+# ---------------------------------------------------------------------------
+# relaxation times tau_4..6 (Eq. 12) act on their own moments of Eq. 11
+# ---------------------------------------------------------------------------
+
+# rows of Eq. 11 that tau_4, tau_5, tau_6 relax, and their equilibria per
+# unit temperature (6 f_0 - sum f_i at f_eq = 6 T/4 - 6 T/8 = 3 T/4; the
+# other two vanish at equilibrium)
+HIGHER_ROWS = {4: ([6, -1, -1, -1, -1, -1, -1], 0.75), 5: ([0, 2, 2, -1, -1, -1, -1], 0.0),
+               6: ([0, 0, 0, 1, 1, -1, -1], 0.0)}
+
+
+@pytest.mark.parametrize("tau_rest", [(0.8, 0.7, 1.6, 1.2), (1.0, 1.9, 0.6, 1.0)])
+def test_each_relaxation_time_acts_on_its_own_moment(tau_rest):
+    """With S block diagonal in the moment basis (Eq. 12), a state that is
+    off equilibrium only in moment k of Eq. 11 keeps that direction, and one
+    collision scales the deviation by 1 - 1/tau_k, the other moments
+    untouched.  tau_4, tau_5, tau_6 differ, so assigning any of them to the
+    wrong row fails."""
+    m = w.random_medium(15, 2, 2, 2, nphase=2)
+    o = make(m, tau_rest=np.array(tau_rest, float))
+    taus = {4: tau_rest[1], 5: tau_rest[2], 6: tau_rest[3]}
+    rng = np.random.default_rng(7)
+    for p in range(2):
+        for k, (row, _) in HIGHER_ROWS.items():
+            phi = np.array(row, float)
+            T = rng.uniform(-1, 1)
+            feq = np.array([T / 4] + [T / 8] * 6)
+            d = 0.37 * phi / (phi @ phi)  # moment k of d is 0.37, every other moment 0
+            out = o.collide_node(p, feq + d)
+            assert np.allclose(out, feq + (1.0 - 1.0 / taus[k]) * d, rtol=0, atol=1e-15), (p, k)
+        # and the equilibria: moment k of f_eq(T) is its row's value
+        for k, (row, per_t) in HIGHER_ROWS.items():
+            assert math.isclose(np.dot(row, [0.25] + [0.125] * 6), per_t, abs_tol=1e-15)
+
+
+@pytest.mark.parametrize("sides", [(0, ADIABATIC, PERIODIC), (0, PERIODIC, ADIABATIC)])
+def test_dense_fixed_point_general_relaxation(sides):
+    """Fixed point with tau_0, tau_4..6 other than 1: the iterated oracle
+    against numpy.linalg.solve of (I - L) f* = b."""
+    tau_rest = (0.9, 0.7, 1.6, 1.2)
+    m = w.random_medium(48, 3, 3, 2, nphase=2, lo=0.3, hi=1.5)
+    fstar, s = mf.fixed_point(m.phase, m.k, 1.0, 0, 1.0, 0.0, sides, tau_rest)
+    o = make(m, grad=0, sides=sides, tau_rest=np.array(tau_rest, float))
+    o.solve(1e-16, TOL_MAXDT, 400000)
+    assert np.allclose(o.get_f(), fstar, rtol=0, atol=1e-12)
+    # a different tau_4..6 gives a different pre-collision fixed point (the
+    # higher moments are not at equilibrium near walls and interfaces)
+    f1, _ = mf.fixed_point(m.phase, m.k, 1.0, 0, 1.0, 0.0, sides)
+    assert np.abs(f1 - fstar).max() > 1e-6
+
+
+# ---------------------------------------------------------------------------
+# start with a flux part: j = -eps tau grad T0 (Eq. 15 read backwards)
+# ---------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("grad", [0, 1, 2])
+def test_flux_start_of_the_linear_solution_is_steady(grad):
+    """A homogeneous anisotropic cell with periodic sides has the steady
+    field T_lin along the gradient axis with the constant flux j = -eps tau
+    grad T (Eq. 15).  Starting from T_lin with that flux part is the steady
+    state itself: a step changes nothing.  The equilibrium start from the
+    same field is not steady."""
+    rng = np.random.default_rng(61 + grad)
+    K = w.random_spd(rng, 0.3, 1.5)
+    shape = [3, 4, 5]  # (nz, ny, nx)
+    shape[2 - grad] = 7
+    m = w.Medium(np.zeros(shape, np.uint8), w.sym6(K)[None, :])
+    n = shape[2 - grad]
+    view = [1, 1, 1]
+    view[2 - grad] = n
+    tlin = np.broadcast_to((0.9 - 1.3 * (np.arange(n) + 0.5) / n).reshape(view), shape).copy()
+    o = Oracle(m.phase, m.k, dmax=0.8)
+    o.set_bc(grad, 0.9, -0.4)
+    o.init(tlin, flux=True)
+    f0 = o.get_f()
+    o.step(1)
+    assert np.allclose(o.get_f(), f0, rtol=0, atol=1e-15)
+    assert o.last_fluxes()["resid"] < 1e-15
+    r = o.keff()
+    assert np.allclose(r["keff_col"], K[:, grad], rtol=1e-12, atol=1e-14)
+    o.init(tlin)
+    fe = o.get_f()
+    o.step(1)
+    assert np.abs(o.get_f() - fe).max() > 1e-3
+
+
+@pytest.mark.parametrize("tau_rest", [(1, 1, 1, 1), (1, 0.7, 1.6, 1.2)])
+def test_flux_start_with_neumann_faces_is_steady(tau_rest):
+    """The side-flux case above (T_lin exact under the linear solution's own
+    side fluxes): the flux start from T_lin is already that steady state; the
+    mirror rule at the Neumann faces sees a field that is uniform across
+    them."""
+    rng = np.random.default_rng(33)
+    K = w.random_spd(rng, 0.3, 1.5)
+    K[0, 2] = K[2, 0] = 0.3
+    K[1, 2] = K[2, 1] = -0.25
+    nx, ny, nz = 5, 4, 9
+    m = w.Medium(np.zeros((nz, ny, nx), np.uint8), w.sym6(K)[None, :])
+    o = make(m, grad=2, sides=(ADIABATIC, ADIABATIC, 0), tau_rest=np.array(tau_rest, float))
+    qx, qy = K[0, 2] / nz, K[1, 2] / nz
+    o.set_side_flux(0, qx, -qx)
+    o.set_side_flux(1, qy, -qy)
+    tlin = np.broadcast_to((1.0 - (np.arange(nz) + 0.5) / nz)[:, None, None], (nz, ny, nx)).copy()
+    o.init(tlin, flux=True)
+    f0 = o.get_f()
+    o.step(3)
+    assert np.allclose(o.get_f(), f0, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("sides", [(0, PERIODIC, ADIABATIC), (ADIABATIC, 0, PERIODIC), (PERIODIC, ADIABATIC, 0)])
+def test_flux_start_gradient_matches_numpy(sides):
+    """Eq. 15 applied to the flux start returns grad T0 by central
+    differences: at every node off the isothermal walls it equals
+    numpy.gradient of T0 padded by wrapping (periodic axis) or by mirroring
+    the edge node (adiabatic face)."""
+    grad_axis = [a for a in range(3) if sides[a] == 0 and a not in
+                 [b for b in range(3) if sides[b] == ADIABATIC]][0]
+    m = w.random_medium(62, 6, 5, 4, nphase=3)
+    rng = np.random.default_rng(9)
+    T0 = rng.uniform(-1, 1, m.phase.shape)
+    side_arg = [PERIODIC if (a == grad_axis) else sides[a] for a in range(3)]
+    o = Oracle(m.phase, m.k)
+    o.set_bc(grad_axis, 1.0, 0.0, side_arg)
+    o.init(T0, flux=True)
+    _, g = o.flux()
+    assert np.allclose(o.temperature(), T0, rtol=0, atol=1e-15)
+    for a in range(3):
+        ax = 2 - a  # array axis of lattice axis a
+        if a == grad_axis:
+            pad = np.pad(T0, [(1, 1) if d == ax else (0, 0) for d in range(3)], mode="edge")  # unused at walls
+        else:
+            mode = "wrap" if side_arg[a] == PERIODIC else "symmetric"
+            pad = np.pad(T0, [(1, 1) if d == ax else (0, 0) for d in range(3)], mode=mode)
+        ref = np.gradient(pad, axis=ax)
+        ref = np.take(ref, range(1, T0.shape[ax] + 1), axis=ax)
+        got = g[a]
+        if a == grad_axis:  # interior nodes only; the wall nodes are pinned by the linear-solution tests
+            sl = [slice(None)] * 3
+            sl[ax] = slice(1, -1)
+            ref, got = ref[tuple(sl)], got[tuple(sl)]
+        assert np.allclose(got, ref, rtol=0, atol=1e-12), a
+
+
+def test_flux_start_translation_equivariance():
+    """Shifting the medium and the start field along the periodic axes
+    shifts the flux start with them (the wrap of Eq. 25)."""
+    m = w.random_medium(63, 5, 6, 4, nphase=3)
+    rng = np.random.default_rng(10)
+    T0 = rng.uniform(-1, 1, m.phase.shape)
+    a = Oracle(m.phase, m.k)
+    a.set_bc(0, 1.0, 0.0)
+    a.init(T0, flux=True)
+    sh = (1, -2)  # (z, y)
+    ms = w.Medium(np.ascontiguousarray(np.roll(m.phase, sh, axis=(0, 1))), m.k)
+    b = Oracle(ms.phase, ms.k)
+    b.set_bc(0, 1.0, 0.0)
+    b.init(np.roll(T0, sh, axis=(0, 1)), flux=True)
+    assert np.allclose(b.get_f(), np.roll(a.get_f(), sh, axis=(1, 2)), rtol=0, atol=1e-15)
