@@ -342,15 +342,16 @@ __device__ __forceinline__ real out_pop(real T, real hj, long long node, int a, 
 // p_ww = f_3 + f_4 - f_5 - f_6) with 1/tau_4..6 of Eq. 12 towards their
 // equilibria (3T/4, 0, 0), then f_hat = M^-1 m_hat using the orthogonality of
 // M's rows (squared norms 7, 2, 2, 2, 42, 12, 4).
+// srel: 1/tau_4, 1/tau_5, 1/tau_6.
 template <typename real>
-__device__ __forceinline__ void relax_general(const Cell<real> &c, real f0, real f1, real f2, real f3, real f4,
+__device__ __forceinline__ void relax_general(const real *srel, real f0, real f1, real f2, real f3, real f4,
                                               real f5, real f6, real T, real hjx, real hjy, real hjz, real *o) {
     const real e = real(6) * f0 - (((((f1 + f2) + f3) + f4) + f5) + f6);
     const real pxx = real(2) * (f1 + f2) - (((f3 + f4) + f5) + f6);
     const real pww = (f3 + f4) - (f5 + f6);
-    const real eh = e - c.srel[0] * (e - real(0.75) * T);
-    const real pxxh = pxx - c.srel[1] * pxx;
-    const real pwwh = pww - c.srel[2] * pww;
+    const real eh = e - srel[0] * (e - real(0.75) * T);
+    const real pxxh = pxx - srel[1] * pxx;
+    const real pwwh = pww - srel[2] * pww;
     const real base = T * real(1.0 / 7.0) - eh * real(1.0 / 42.0);
     const real ax = base + pxxh * real(1.0 / 6.0);
     const real ay = (base - pxxh * real(1.0 / 12.0)) + pwwh * real(0.25);
@@ -416,7 +417,7 @@ __device__ __forceinline__ void collide_store(const Cell<real> &c, const real *_
         Z_.v[v] = hjz;
         if constexpr (STORAGE == 2) {
             real o[Q];
-            relax_general(c, f0, f1, f2, f3, f4, f5, f6, T, hjx, hjy, hjz, o);
+            relax_general(c.srel, f0, f1, f2, f3, f4, f5, f6, T, hjx, hjy, hjz, o);
 #pragma unroll
             for (int i = 0; i < Q; i++) G_[i].v[v] = o[i];
         }
@@ -687,38 +688,53 @@ __device__ __forceinline__ void collide_store_exact(const Cell<float> &c, const 
     }
 }
 
-// FP32 population storage: T, j and jhat in FP64 from the FP32 inputs, the
-// seven outputs T/4, T/8 +- jhat_a/2 formed exactly in FP64 and each
-// dithered to FP32 (these are the only roundings of the step).
-template <int VEC, int MODE, int NT>
+// FP32 population storage: the pulled populations with their gradient-axis
+// shift, T, j and jhat all in FP64 from the FP32 inputs (exact sums and
+// differences), the seven outputs -- T/4, T/8 +- jhat_a/2, or with RELAX the
+// general relaxation of the three remaining moments (Eq. 12, tau_4..6 not
+// all 1) -- formed in FP64 and each dithered to FP32: these are the only
+// roundings of the step.
+template <int VEC, int MODE, int NT, bool RELAX>
 __device__ __forceinline__ void collide_store_pop32(const Cell<float> &c, const float *__restrict__ tab, int xv, int y,
                                                     int z, bool active, const Pulled<float, VEC> &P, Acc &acc,
                                                     float *__restrict__ qout, float qscale) {
     const long long N = c.N;
     const long long base = ((long long)z * c.ny + y) * c.nx + xv * VEC;
-    const float hx = c.h[0], hy = c.h[1], hz = c.h[2];
+    const double hx = c.h[0], hy = c.h[1], hz = c.h[2];
+    double srel[3];
+    if constexpr (RELAX) {
+        srel[0] = c.srel[0];
+        srel[1] = c.srel[1];
+        srel[2] = c.srel[2];
+    }
     Vec<float, VEC> G[Q];
 #pragma unroll
     for (int v = 0; v < VEC; v++) {
-        const float f0 = P.f0[v];
-        const float f1 = P.r[0][v] + hx, f2 = P.r[1][v] - hx;
-        const float f3 = P.r[2][v] + hy, f4 = P.r[3][v] - hy;
-        const float f5 = P.r[4][v] + hz, f6 = P.r[5][v] - hz;
-        const double T = (((((((double)f0 + (double)f1) + (double)f2) + (double)f3) + (double)f4) + (double)f5) +
-                          (double)f6);
-        const double jx = (double)f1 - (double)f2, jy = (double)f3 - (double)f4, jz = (double)f5 - (double)f6;
+        const double f0 = P.f0[v];
+        const double f1 = (double)P.r[0][v] + hx, f2 = (double)P.r[1][v] - hx;
+        const double f3 = (double)P.r[2][v] + hy, f4 = (double)P.r[3][v] - hy;
+        const double f5 = (double)P.r[4][v] + hz, f6 = (double)P.r[5][v] - hz;
+        const double T = ((((((f0 + f1) + f2) + f3) + f4) + f5) + f6);
+        const double jx = f1 - f2, jy = f3 - f4, jz = f5 - f6;
         const float *tb = tab + P.ph[v] * TABW;  // half of (I - tau^-1)
         const double hjx = fma((double)tb[4], jz, fma((double)tb[3], jy, (double)tb[0] * jx));
         const double hjy = fma((double)tb[5], jz, fma((double)tb[1], jy, (double)tb[3] * jx));
         const double hjz = fma((double)tb[2], jz, fma((double)tb[5], jy, (double)tb[4] * jx));
         const unsigned long long key = (unsigned long long)(base + v) * 8ull;
-        G[0].v[v] = dither_to_float(T * 0.25, key);
-        G[1].v[v] = dither_to_float(fma(T, 0.125, hjx), key + 1);
-        G[2].v[v] = dither_to_float(fma(T, 0.125, -hjx), key + 2);
-        G[3].v[v] = dither_to_float(fma(T, 0.125, hjy), key + 3);
-        G[4].v[v] = dither_to_float(fma(T, 0.125, -hjy), key + 4);
-        G[5].v[v] = dither_to_float(fma(T, 0.125, hjz), key + 5);
-        G[6].v[v] = dither_to_float(fma(T, 0.125, -hjz), key + 6);
+        if constexpr (RELAX) {
+            double o[Q];
+            relax_general<double>(srel, f0, f1, f2, f3, f4, f5, f6, T, hjx, hjy, hjz, o);
+#pragma unroll
+            for (int i = 0; i < Q; i++) G[i].v[v] = dither_to_float(o[i], key + i);
+        } else {
+            G[0].v[v] = dither_to_float(T * 0.25, key);
+            G[1].v[v] = dither_to_float(fma(T, 0.125, hjx), key + 1);
+            G[2].v[v] = dither_to_float(fma(T, 0.125, -hjx), key + 2);
+            G[3].v[v] = dither_to_float(fma(T, 0.125, hjy), key + 3);
+            G[4].v[v] = dither_to_float(fma(T, 0.125, -hjy), key + 4);
+            G[5].v[v] = dither_to_float(fma(T, 0.125, hjz), key + 5);
+            G[6].v[v] = dither_to_float(fma(T, 0.125, -hjz), key + 6);
+        }
         if constexpr (MODE != 0) {
             if (active) {
                 // T(t+1) as the next step sums it; the rounding energy is its
@@ -769,10 +785,10 @@ __device__ __forceinline__ void node_update(const Cell<real> &c, const real *__r
         PulledX<VEC, MODE> P;
         pull_mom_exact<VEC, MODE, NT>(c, xv, y, z, xl, P);
         collide_store_exact<VEC, MODE, NT>(c, tab, xv, y, z, active, P, acc, qout, qscale);
-    } else if constexpr (STORAGE == 0 && sizeof(real) == 4) {
+    } else if constexpr ((STORAGE == 0 || STORAGE == 2) && sizeof(real) == 4) {
         Pulled<float, VEC> P;
         pull_dist<float, VEC, MODE, NT>(c, xv, y, z, xl, P);
-        collide_store_pop32<VEC, MODE, NT>(c, tab, xv, y, z, active, P, acc, qout, qscale);
+        collide_store_pop32<VEC, MODE, NT, STORAGE == 2>(c, tab, xv, y, z, active, P, acc, qout, qscale);
     } else {
         Pulled<real, VEC> P;
         if constexpr (STORAGE == 1) pull_mom<real, VEC, MODE, NT>(c, xv, y, z, xl, P);

@@ -1,13 +1,17 @@
-"""The paper's braided unit cell (Eqs. 32-37) on the synthetic braid: the
-qualitative results of Sec. 5.2 (Fig. 9 trends; periodic vs adiabatic sides).
+"""The paper's braided unit cell (Eqs. 32-37) on the synthetic braid.
 
-Absolute values are not compared: the paper's yarn coordinates are not given
-(parity unpinned); only the trends it reports are checked, at a coarse grid
-(28 voxels across instead of 56)."""
+The GPU path on this cell against the FP64 oracle (200-step windows at the
+paper's 56 x 56 x 120 grid and at half that resolution, every boundary
+combination of Sec. 5.2), the FP32 k_eff against a converged FP64 solve, and
+the qualitative results of Sec. 5.2 (Fig. 9 trends; periodic vs adiabatic
+sides).  The paper's own k values are not compared: its yarn coordinates are
+not given (parity unpinned); only the trends it reports are checked."""
 
+import numpy as np
 import pytest
 
 import workloads as w
+from oracle import ADIABATIC, PERIODIC, Oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -37,6 +41,60 @@ def results():
             for (g, phi, _), r in zip(specs, res):
                 out[(g, phi, sides, axis)] = r["keff"]
     return out
+
+
+@pytest.fixture(scope="module")
+def Medium():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device")
+    from paper_1503_08718_amd.solver import Medium
+
+    return Medium
+
+
+@pytest.mark.parametrize("nxy", [28, 56])
+@pytest.mark.parametrize("axis,sides", [(0, "periodic"), (2, "periodic"), (0, "adiabatic"), (2, "adiabatic")])
+@pytest.mark.parametrize("storage", ["moments", "populations"])
+def test_paper_cell_matches_oracle(Medium, nxy, axis, sides, storage):
+    """gamma = 25 deg, phi_f = 0.5: 200 FP64 steps from a smooth random start
+    (every node moves from the first step), field within 1e-12 of the oracle,
+    wall and volume fluxes of the next step within 1e-10."""
+    m, geo = w.paper_unit_cell(25.0, 0.5, nxy)
+    assert (geo["nx"], geo["nz"]) == (nxy, {28: 60, 56: 120}[nxy])
+    nz, ny, nx = m.phase.shape
+    rng = np.random.default_rng(nxy + axis)
+    z, y, x = np.meshgrid(*(np.linspace(0, 2 * np.pi, n, endpoint=False) for n in (nz, ny, nx)), indexing="ij")
+    T0 = 0.5 + 0.3 * np.sin(x + rng.uniform(0, 6)) * np.cos(2 * y) + 0.1 * np.sin(3 * z)
+    side = PERIODIC if sides == "periodic" else ADIABATIC
+    g = Medium(m.phase, m.k, precision="f64", storage=storage).set_bc(axis, 1.0, 0.0, (sides,) * 3).init(T0)
+    o = Oracle(m.phase, m.k)
+    o.set_bc(axis, 1.0, 0.0, (side,) * 3)
+    o.init(T0)
+    g.step(200)
+    o.step(200)
+    to = o.temperature()
+    assert np.abs(g.temperature().cpu().numpy() - to).max() < 1e-12 * np.abs(to).max()
+    kg = g.keff()
+    o.step(1)
+    ko = o.keff()
+    for key in ("keff_hot", "keff_cold", "keff_vol"):
+        assert abs(kg[key] - ko[key]) < 1e-10 * max(1.0, abs(ko[key])), key
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+def test_paper_cell_fp32_keff_close_to_fp64(Medium, axis):
+    """The paper's 56 x 56 x 120 cell (gamma = 25 deg, phi_f = 0.5, periodic
+    sides): FP32 at the production tolerance 1e-4 against FP64 converged to
+    1e-8, both from a zero start."""
+    m, _ = w.paper_unit_cell(25.0, 0.5, 56)
+    r = {}
+    for prec, tol in (("f64", 1e-8), ("f32", 1e-4)):
+        g = Medium(m.phase, m.k, precision=prec).set_bc(axis, 1.0, 0.0, ("periodic",) * 3).init()
+        r[prec] = g.solve(tol, "keff", 4_000_000, check_every=1000)
+        assert r[prec]["converged"], (prec, r[prec])
+    assert abs(r["f32"]["keff"] - r["f64"]["keff"]) < 1e-4 * r["f64"]["keff"]
 
 
 def test_transverse_rises_and_longitudinal_falls_with_braiding_angle(results):

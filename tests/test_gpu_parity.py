@@ -181,6 +181,55 @@ def test_warm_start_init_matches_oracle(Medium):
     assert field_err(g, o) < 1e-12
 
 
+# every wall mix, both storages: the start with a flux part (Eq. 15 read
+# backwards, grad T0 by central differences) against the oracle's own
+FLUX_START_CASES = CASES + [(9, 8, 7, 3, 2, (PERIODIC, ADIABATIC, 0), 10), (5, 1, 3, 2, 1, (ADIABATIC, 0, PERIODIC), 11),
+                            (2, 2, 2, 2, 0, (0, ADIABATIC, ADIABATIC), 12)]
+
+
+@pytest.mark.parametrize("storage", ["populations", "moments"])
+@pytest.mark.parametrize("case", FLUX_START_CASES, ids=lambda c: "x".join(map(str, c[:3])) + f"_g{c[4]}")
+def test_flux_start_matches_oracle(Medium, case, storage):
+    nx, ny, nz, nph, grad, sides, seed = case
+    m = w.random_medium(70 + seed, nx, ny, nz, nph)
+    rng = np.random.default_rng(70 + seed)
+    T0 = rng.uniform(-0.5, 1.5, m.phase.shape)
+    g = Medium(m.phase, m.k, precision="f64", storage=storage)
+    g.set_bc(grad, 0.8, -0.4, [SIDE_NAMES[s] for s in sides]).init(T0, flux=True)
+    o = Oracle(m.phase, m.k)
+    o.set_bc(grad, 0.8, -0.4, sides)
+    o.init(T0, flux=True)
+    assert field_err(g, o) < 1e-14
+    for n in (1, 9, 50):
+        g.step(n)
+        o.step(n)
+        assert field_err(g, o) < 1e-12, n
+    kg = g.keff()
+    o.step(1)
+    ko = o.keff()
+    for key in ("keff_hot", "keff_cold", "keff_vol"):
+        assert abs(kg[key] - ko[key]) < 1e-10 * max(1.0, abs(ko[key])), key
+    # the flux part matters: the equilibrium start from the same field differs
+    o.init(T0)
+    o.step(61)
+    assert field_err(g, o) > 1e-9
+
+
+def test_flux_start_fp32_matches_oracle(Medium):
+    m = w.braid(24, 20, 16, 35.0, 0.5)
+    rng = np.random.default_rng(75)
+    T0 = 0.5 + 0.3 * rng.standard_normal(m.phase.shape) * 0.1
+    for storage in ("populations", "moments"):
+        g = Medium(m.phase, m.k, precision="f32", storage=storage)
+        g.set_bc(2, 1.0, 0.0, ["periodic", "adiabatic", "periodic"]).init(T0, flux=True)
+        o = Oracle(m.phase, m.k)
+        o.set_bc(2, 1.0, 0.0, (PERIODIC, ADIABATIC, 0))
+        o.init(T0, flux=True)
+        g.step(40)
+        o.step(40)
+        assert field_err(g, o) < 2e-6, storage
+
+
 def test_fp32_close_to_fp64(Medium):
     # FP32 at the production tolerance (wall-flux gap 1e-4) against an FP64
     # solve converged far tighter
@@ -463,6 +512,39 @@ def test_general_relaxation_matches_oracle(Medium, case):
     h = Medium(m.phase, m.k, precision="f64").set_bc(grad, 1.0, 0.0, [SIDE_NAMES[s] for s in sides]).init()
     h.step(400)
     assert field_err(h, o) > 1e-9
+
+
+def test_fp32_general_relaxation_matches_oracle(Medium):
+    """FP32 population storage with tau_4..6 other than 1: the seven outputs
+    of the general relaxation are formed in FP64 and dithered like the
+    others; a 300-step window stays on the oracle to FP32 noise."""
+    m = w.random_medium(44, 16, 12, 10, 4)
+    rng = np.random.default_rng(44)
+    T0 = rng.uniform(0.0, 1.0, m.phase.shape)
+    g = Medium(m.phase, m.k, precision="f32").set_bc(0, 1.0, 0.0, ["periodic", "adiabatic", "periodic"])
+    g.set_relaxation(*TAU_REST).init(T0)
+    o = Oracle(m.phase, m.k, tau_rest=np.array((1.0,) + TAU_REST))
+    o.set_bc(0, 1.0, 0.0, (0, ADIABATIC, PERIODIC))
+    o.init(T0)
+    g.step(300)
+    o.step(300)
+    assert field_err(g, o) < 2e-6
+
+
+def test_fp32_general_relaxation_close_to_fp64(Medium):
+    """64^3 braided cell, adiabatic sides, tau_4..6 = (0.7, 1.6, 1.2): the
+    FP32 solve lands within 2e-6 of the FP64 answer, with no rounding
+    floor."""
+    m = w.braid(64, 64, 64, 30.0, 0.5)
+    sides = ("periodic", "adiabatic", "adiabatic")
+    g64 = Medium(m.phase, m.k, precision="f64").set_bc(0, 1.0, 0.0, sides).set_relaxation(*TAU_REST).init()
+    r64 = g64.solve(1e-9, "keff", 4_000_000, check_every=1000)
+    g32 = Medium(m.phase, m.k, precision="f32").set_bc(0, 1.0, 0.0, sides).set_relaxation(*TAU_REST).init()
+    r32 = g32.solve(1e-6, "keff", 4_000_000, check_every=1000)
+    assert r64["converged"] and r32["converged"], (r64, r32)
+    assert rel(r32["keff"], r64["keff"]) < 2e-6, (r32, r64)
+    assert rel(r32["keff_vol"], r64["keff_vol"]) < 2e-6
+    assert abs(r32["keff_leak"]) < 1e-5 * r32["keff"]
 
 
 @pytest.mark.parametrize("storage", ["populations", "moments"])

@@ -35,6 +35,7 @@ from .media import (  # noqa: F401
 from .unitcell import (  # noqa: F401
     PHI_Y_EXACT,
     PHI_Y_ROUNDED,
+    paper_unit_cell,
     unit_cell_geometry,
     yarn_conductivities,
 )

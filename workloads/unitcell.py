@@ -51,3 +51,20 @@ def yarn_conductivities(phi_f: float, lam_f_long: float = 7.81, lam_f_trans: flo
     lam_l = lam_f_long * phi_fy + lam_m * (1.0 - phi_fy)
     lam_t = lam_m + phi_fy / (1.0 / (lam_f_trans - lam_m) + (1.0 - phi_fy) / (2.0 * lam_m))
     return lam_l, lam_t
+
+
+def paper_unit_cell(gamma_deg: float, phi_f: float, nxy: int = 56, lam_f_long: float = 7.81,
+                    lam_f_trans: float = 0.675, lam_m: float = 0.178):
+    """The paper's unit cell on the synthetic braid: an a x a x h box of
+    Eqs. 32-35 with ``nxy`` voxels across (nz = nxy h / a rounded to an even
+    count), yarn fraction phi_y = pi sqrt(3) / 8 (Eq. 35), yarn tensors from
+    Eqs. 36-37 and an isotropic epoxy matrix.  Sec. 5's example grid is
+    56 x 56 x 120 at gamma = 25 deg.  Returns (medium, geometry dict)."""
+    from .media import braid
+
+    geo = unit_cell_geometry(phi_f, gamma_deg)
+    nz = int(round(nxy * geo["h"] / geo["a"]))
+    nz += nz % 2
+    lam_l, lam_t = yarn_conductivities(phi_f, lam_f_long, lam_f_trans, lam_m)
+    m = braid(nxy, nxy, nz, gamma_deg, PHI_Y_EXACT, lam_l, lam_t, lam_m)
+    return m, dict(geo, nx=nxy, ny=nxy, nz=nz, lam_l=lam_l, lam_t=lam_t, gamma=gamma_deg, phi_f=phi_f)
