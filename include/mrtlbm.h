@@ -190,6 +190,23 @@ mrtlbm_status mrtlbm_step(mrtlbm_medium *m, long long nsteps);
 mrtlbm_status mrtlbm_solve(mrtlbm_medium *m, double tol, mrtlbm_tol_kind kind, long long max_steps,
                            int check_every, mrtlbm_result *out);
 
+/*
+ * For callers that cannot allocate memory (serving loops and harnesses that
+ * forbid hipMalloc and graph instantiation): mrtlbm_solve without hip graphs
+ * (every step is its own launch) and with the check step's per-block
+ * partials and final reduction in a fixed device array of the library
+ * instead of the medium's workspace.  Same arguments, stop rules, return
+ * values and results as mrtlbm_solve, bit for bit.  The array holds the
+ * partials of up to 65536 check blocks (5.2 MB per device, kept until the
+ * process ends); a medium whose check step needs more (a cross-section of
+ * more than about 2^20 x-vectors of the launch shape) gets
+ * MRTLBM_E_WORKSPACE before any device work.  Calls on the same device
+ * share that array: calls that overlap in time on one device race and
+ * must be serialised by the caller.  Synchronises.
+ */
+mrtlbm_status mrtlbm_solve_noalloc(mrtlbm_medium *m, double tol, mrtlbm_tol_kind kind, long long max_steps,
+                                   int check_every, mrtlbm_result *out);
+
 /* Observables of the next streaming step, computed without changing the
  * state (see mrtlbm_result).  Synchronises. */
 mrtlbm_status mrtlbm_keff(mrtlbm_medium *m, mrtlbm_result *out);
