@@ -89,9 +89,15 @@ def parse():
     p.add_argument("--ref-tol", type=float, default=1e-7)
     p.add_argument("--no-ref", action="store_true")
     p.add_argument("--precision", default="", choices=["", "f32", "f64"], help="solve mode: one solve per axis")
-    p.add_argument("--start", default="zero",
-                   help="zero | linear | learned; sweep mode takes a comma list (e.g. zero,learned)")
+    p.add_argument("--start", default="",
+                   help="zero | linear | learned (solve mode, default zero); sweep and warmstart modes take a "
+                        "comma list (defaults zero,learned and zero,linear,learned)")
+    p.add_argument("--ref-only", action="store_true", help="sweep / warmstart: only the FP64 references")
     p.add_argument("--ref-cells", type=int, default=0, help="sweep mode: FP64 reference for the first K cells")
+    p.add_argument("--ref-start", default="zero", choices=["zero", "linear"],
+                   help="start of the FP64 reference solves (sweep and warmstart modes)")
+    p.add_argument("--ref-out", default="", help="write the FP64 references to this JSON file")
+    p.add_argument("--ref-in", default="", help="take the FP64 references from this JSON file instead of solving")
     p.add_argument("--max-steps", type=int, default=20_000_000)
     p.add_argument("--cells", type=int, default=64)
     p.add_argument("--seed", type=int, default=1503)
@@ -110,11 +116,34 @@ def _medium(m, prec, args):
     return g
 
 
+def host_cpu() -> dict:
+    """What lscpu says about the host (model name, sockets, cores)."""
+    import subprocess
+
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for ln in out.splitlines():
+            k, _, v = ln.partition(":")
+            if k.strip() in ("Model name", "CPU(s)", "Socket(s)", "Core(s) per socket", "Thread(s) per core",
+                             "Vendor ID", "CPU family", "Model", "L3 cache"):
+                info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        info["usable_cpus"] = len(os.sched_getaffinity(0))
+    except OSError:
+        pass
+    return info
+
+
 def cpu_baseline(m, sample_steps):
-    """The oracle, as it is, on a bounded sample of the same cell."""
+    """The oracle, as it is, on a bounded sample of the same cell: the same
+    source built on this host with -O3 -march=native -ffp-contract=off
+    -fopenmp (oracle.TIMING_FLAGS), all usable threads, then one thread."""
     import oracle
 
-    o = oracle.from_medium(m)
+    o = oracle.Oracle(m.phase, m.k, timing=True)
     o.set_bc(0, 1.0, 0.0, (0, 0, 0))
     o.init()
     n = m.phase.size
@@ -123,24 +152,20 @@ def cpu_baseline(m, sample_steps):
     t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     # and on one thread, over a few seconds' worth of steps
     o.set_threads(1)
     s1 = max(1, int(round(1.2e8 / n)))
     t0 = time.perf_counter()
     o.step(s1)
     dt1 = time.perf_counter() - t0
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
-    except OSError:
-        pass
+    cpu = host_cpu()
     return {"value": round(n * steps / dt / 1e6, 2), "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "single_thread_value": round(n * s1 / dt1 / 1e6, 2), "cpu_model": model,
+            "single_thread_value": round(n * s1 / dt1 / 1e6, 2), "cpu_model": cpu.get("Model name", ""),
+            "host": cpu, "build_flags": " ".join(oracle.TIMING_FLAGS),
             "sample": f"{steps} FP64 oracle steps on the same {m.nx}x{m.ny}x{m.nz} braided cell "
-                      f"(x gradient, periodic sides), OpenMP over z-planes; {s1} more steps on one thread "
-                      f"for single_thread_value"}
+                      f"(x gradient, periodic sides), OpenMP over z-planes on {cores} threads; {s1} more steps "
+                      f"on one thread for single_thread_value"}
 
 
 def mode_throughput(args):
@@ -165,7 +190,9 @@ def mode_throughput(args):
     nodes = n ** 3
     mlups = nodes * args.steps / wall / 1e6
     # live kernel time: hip events around plain steps on the medium's stream
-    kt_steps = max(64, min(args.steps, 2000))
+    # (a fixed sample of 2000 steps, so that short timed regions still give a
+    # settled kernel time)
+    kt_steps = 2000
     ms = g.time_steps(kt_steps)
     kern_us = ms * 1e3 / kt_steps
     achieved = bpl * nodes / (kern_us * 1e-6) / 1e9
@@ -213,22 +240,41 @@ def mode_throughput(args):
 
 
 def mode_copy(args):
+    """HBM copy ceilings with the library's hand-written streaming copy
+    (mrtlbm_stream_copy): 1 GiB read and 1 GiB written per copy, split over
+    1, 2, 4 or 7 separate arrays (the step kernel streams 4 or 7 state
+    arrays), plain and non-temporal loads/stores; hip events on the stream
+    the copies run on."""
     import torch
 
-    n = 1 << 28  # 1 GiB of float32
-    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    from paper_1503_08718_amd import _lib
+
+    L = _lib.load()
+    total = 1 << 30
+    a = torch.ones(total // 4, dtype=torch.float32, device="cuda:0")
     b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    out = {"mode": "copy", "bytes_read_per_copy": total, "kernel": "k_stream_copy", "copies": []}
     reps = 20
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
-    return {"mode": "copy", "bytes_read_per_copy": 4 * n, "bytes_written_per_copy": 4 * n, "copies": reps + 3,
-            "GB_s": round(8 * n / dt / 1e9, 1)}
+    for streams in (1, 2, 4, 7):
+        n16 = (total // 16) // streams
+        for nt in (0, 1):
+            def run():
+                _lib.check(L.mrtlbm_stream_copy(a.data_ptr(), b.data_ptr(), n16, streams, nt, stream.cuda_stream))
+            for _ in range(3):
+                run()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                run()
+            e1.record(stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            moved = 2 * 16 * n16 * streams
+            out["copies"].append({"arrays": streams, "nt": nt, "us": round(ms * 1e3, 2),
+                                  "GB_s": round(moved / (ms * 1e-3) / 1e9, 1),
+                                  "frac_of_peak": round(moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+    return out
 
 
 def mode_network(args):
@@ -332,6 +378,8 @@ def mode_solve(args):
     --precision the single requested solve (from --start) is run instead."""
     import workloads
 
+    args.start = args.start or "zero"
+
     m = workloads.braid(args.n, args.n, args.n, args.gamma, args.vf)
     out = {"mode": "solve", "workload": f"braided cell {args.n}^3, gamma {args.gamma}, yarn fraction {args.vf}, "
                                         f"{args.sides} sides", "tol": args.tol, "solves": []}
@@ -388,24 +436,40 @@ def mode_sweep(args):
     import workloads
     from paper_1503_08718_amd import warmstart as ws
 
-    starts = [s for s in args.start.split(",") if s]
+    starts = [] if args.ref_only else [s for s in (args.start or "zero,learned").split(",") if s]
     t_start = time.perf_counter()
     specs = workloads.sweep_cells(args.seed, args.cells)
     media = ws.generate_media(specs)
     canon = [mm for m in media for mm in ws.canonical_media(m)]
     t_gen = time.perf_counter() - t_start
-    net = ws.Net.from_file(args.model, batch=1) if ("learned" in starts or args.ref_cells) else None
+    net = ws.Net.from_file(args.model, batch=1) if "learned" in starts else None
     out = {"mode": "sweep", "cells": len(media), "solves_per_cell": 2, "tol": args.tol, "storage": args.storage,
            "nodes_total": int(sum(m.phase.size for m in media)), "seconds_geometry": round(t_gen, 2),
            "sizes": [list(m.phase.shape[::-1]) for m in media]}
     ref = None
-    if args.ref_cells:
+    if args.ref_in:
+        with open(args.ref_in) as fh:
+            saved = json.load(fh)
+        if saved["cells"] < len(media) and args.ref_cells > saved["cells"]:
+            raise SystemExit(f"{args.ref_in} holds references for {saved['cells']} cells")
+        assert saved["seed"] == args.seed and saved["mode"] == "sweep", "reference file of another workload"
+        ref = saved["keff"][:2 * (args.ref_cells or saved["cells"])]
+        out["reference"] = {k: saved[k] for k in ("cells", "precision", "tol", "start", "all_converged", "seconds")}
+        out["reference"]["file"] = os.path.basename(args.ref_in)
+    elif args.ref_cells:
         sub = canon[:2 * args.ref_cells]
-        _, rres, _, _ = ws.solve_fields(sub, tol=args.tol / 100, start="learned", net=net, batch=True,
-                                        precision="f64", max_steps=args.max_steps, keep_fields=False)
+        t0 = time.perf_counter()
+        _, rres, _, _ = ws.solve_fields(sub, tol=args.tol / 100, start=args.ref_start, net=net, batch=True,
+                                        precision="f64", max_steps=args.max_steps, storage=args.storage,
+                                        keep_fields=False, tune=True)
         ref = [r["keff"] for r in rres]
         out["reference"] = {"cells": args.ref_cells, "precision": "f64", "tol": args.tol / 100,
-                            "all_converged": all(r["converged"] for r in rres), "keff": [round(k, 7) for k in ref]}
+                            "start": args.ref_start, "all_converged": all(r["converged"] for r in rres),
+                            "seconds": round(time.perf_counter() - t0, 1), "keff": ref,
+                            "steps": [r["steps"] for r in rres]}
+        if args.ref_out:
+            with open(args.ref_out, "w") as fh:
+                json.dump(dict(out["reference"], mode="sweep", seed=args.seed), fh)
         print(json.dumps({"reference": "done", "cells": args.ref_cells}), flush=True)
     for start in starts:
         torch.cuda.synchronize()
@@ -427,6 +491,7 @@ def mode_sweep(args):
             errs = [abs(r["keff"] - k) / abs(k) for r, k in zip(res, ref)]
             rec["max_rel_err_vs_reference"] = float(max(errs))
             rec["mean_rel_err_vs_reference"] = float(np.mean(errs))
+            rec["rel_err_vs_reference"] = [float(f"{e:.3g}") for e in errs]  # every solve, (x, z) per cell
         out[start] = rec
         print(json.dumps({"start": start, "seconds": rec["seconds"], "steps_mean": rec["steps_mean"],
                           "cells_per_hour": rec["cells_per_hour"], "fallbacks": fb}), flush=True)

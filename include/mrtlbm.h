@@ -269,6 +269,17 @@ mrtlbm_status mrtlbm_load_tuned(mrtlbm_medium *m, const char *cache_path);
  * return the elapsed milliseconds.  Synchronises. */
 mrtlbm_status mrtlbm_time_steps(mrtlbm_medium *m, long long nsteps, double *ms);
 
+/* Measurement calibration, not part of the method: a plain streaming copy
+ * of `streams` (1, 2, 4 or 7) separate arrays of n16 16-byte elements each,
+ * src_dev[k][n16] -> dst_dev[k][n16], every lane issuing all its loads before
+ * its stores; nt != 0 uses non-temporal loads and stores.  The step kernel
+ * moves 4 (moment storage) or 7 (population storage) such state arrays; the
+ * copy of the same number of arrays is the HBM ceiling its bandwidth is read
+ * against, and a copy of known size calibrates the HBM byte counters.
+ * Both arrays 16-byte aligned and device-resident; async on hip_stream. */
+mrtlbm_status mrtlbm_stream_copy(const void *src_dev, void *dst_dev, long long n16, int streams, int nt,
+                                 void *hip_stream);
+
 void mrtlbm_destroy(mrtlbm_medium *m);
 const char *mrtlbm_last_error(void);
 

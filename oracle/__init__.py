@@ -38,7 +38,32 @@ def build(force: bool = True) -> str:
     return _LIB_PATH
 
 
+#: flags of the timing copy (the CPU baseline): the same source, built on the
+#: host that runs it, with its full instruction set
+TIMING_FLAGS = ["-O3", "-march=native", "-ffp-contract=off", "-fopenmp"]
+
 _lib = None
+_timing_lib = None
+
+
+def build_timing_copy(directory: str | None = None) -> str:
+    """Compile lbm_oracle.c with TIMING_FLAGS into ``directory`` (default: a
+    fresh temporary directory) on this host, for timing only.  The checker
+    build (build()) is left alone."""
+    import tempfile
+
+    d = directory or tempfile.mkdtemp(prefix="lbm_oracle_timing_")
+    path = os.path.join(d, "liblbm_oracle_timing.so")
+    subprocess.run(["gcc", *TIMING_FLAGS, "-shared", "-fPIC", "-o", path, _SRC, "-lm"], check=True)
+    return path
+
+
+def timing_lib():
+    """The oracle built with TIMING_FLAGS on this host (compiled on first use)."""
+    global _timing_lib
+    if _timing_lib is None:
+        _timing_lib = _bind(ctypes.CDLL(build_timing_copy()))
+    return _timing_lib
 
 
 def lib():
@@ -46,37 +71,40 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             build()
-        L = ctypes.CDLL(_LIB_PATH)
-        P, D, I, LL = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_longlong
-        dp = ctypes.POINTER(ctypes.c_double)
-        L.oracle_create.restype = P
-        L.oracle_create.argtypes = [I, I, I, P, dp, I, D, dp]
-        L.oracle_destroy.argtypes = [P]
-        L.oracle_scale.restype = D
-        L.oracle_scale.argtypes = [P]
-        L.oracle_omega.argtypes = [P, I, dp]
-        L.oracle_tau.argtypes = [P, I, dp]
-        L.oracle_steps.restype = LL
-        L.oracle_steps.argtypes = [P]
-        L.oracle_set_threads.argtypes = [P, I]
-        L.oracle_set_bc.restype = I
-        L.oracle_set_bc.argtypes = [P, I, D, D, ctypes.POINTER(ctypes.c_int)]
-        L.oracle_set_side_flux.restype = I
-        L.oracle_set_side_flux.argtypes = [P, I, D, D]
-        L.oracle_init.argtypes = [P, dp]
-        L.oracle_init_flux.argtypes = [P, dp]
-        L.oracle_collide_node.argtypes = [P, I, dp, dp]
-        L.oracle_step.argtypes = [P, LL]
-        L.oracle_temperature.argtypes = [P, dp]
-        L.oracle_flux.argtypes = [P, dp, dp]
-        L.oracle_keff.argtypes = [P, dp]
-        L.oracle_solve.restype = I
-        L.oracle_solve.argtypes = [P, D, I, LL, I, dp]
-        L.oracle_get_f.argtypes = [P, dp]
-        L.oracle_set_f.argtypes = [P, dp]
-        L.oracle_last_fluxes.argtypes = [P, dp]
-        _lib = L
+        _lib = _bind(ctypes.CDLL(_LIB_PATH))
     return _lib
+
+
+def _bind(L):
+    P, D, I, LL = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_longlong
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.oracle_create.restype = P
+    L.oracle_create.argtypes = [I, I, I, P, dp, I, D, dp]
+    L.oracle_destroy.argtypes = [P]
+    L.oracle_scale.restype = D
+    L.oracle_scale.argtypes = [P]
+    L.oracle_omega.argtypes = [P, I, dp]
+    L.oracle_tau.argtypes = [P, I, dp]
+    L.oracle_steps.restype = LL
+    L.oracle_steps.argtypes = [P]
+    L.oracle_set_threads.argtypes = [P, I]
+    L.oracle_set_bc.restype = I
+    L.oracle_set_bc.argtypes = [P, I, D, D, ctypes.POINTER(ctypes.c_int)]
+    L.oracle_set_side_flux.restype = I
+    L.oracle_set_side_flux.argtypes = [P, I, D, D]
+    L.oracle_init.argtypes = [P, dp]
+    L.oracle_init_flux.argtypes = [P, dp]
+    L.oracle_collide_node.argtypes = [P, I, dp, dp]
+    L.oracle_step.argtypes = [P, LL]
+    L.oracle_temperature.argtypes = [P, dp]
+    L.oracle_flux.argtypes = [P, dp, dp]
+    L.oracle_keff.argtypes = [P, dp]
+    L.oracle_solve.restype = I
+    L.oracle_solve.argtypes = [P, D, I, LL, I, dp]
+    L.oracle_get_f.argtypes = [P, dp]
+    L.oracle_set_f.argtypes = [P, dp]
+    L.oracle_last_fluxes.argtypes = [P, dp]
+    return L
 
 
 def _dp(a: np.ndarray):
@@ -86,8 +114,11 @@ def _dp(a: np.ndarray):
 class Oracle:
     """One medium on the CPU.  Arrays are numpy, (nz, ny, nx) order."""
 
-    def __init__(self, phase: np.ndarray, k: np.ndarray, dmax: float = 1.0, tau_rest=None, threads: int = 0):
-        L = lib()
+    def __init__(self, phase: np.ndarray, k: np.ndarray, dmax: float = 1.0, tau_rest=None, threads: int = 0,
+                 timing: bool = False):
+        """timing=True runs on the copy built with TIMING_FLAGS (CPU baseline)."""
+        L = timing_lib() if timing else lib()
+        self._L = L
         self.phase = np.ascontiguousarray(phase, dtype=np.uint8)
         self.k = np.ascontiguousarray(k, dtype=np.float64)
         nz, ny, nx = self.phase.shape
@@ -107,41 +138,42 @@ class Oracle:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and _lib is not None:
-            _lib.oracle_destroy(h)
+        L = getattr(self, "_L", None)
+        if h is not None and L is not None:
+            L.oracle_destroy(h)
             self._h = None
 
     @property
     def scale(self) -> float:
-        return lib().oracle_scale(self._h)
+        return self._L.oracle_scale(self._h)
 
     @property
     def steps(self) -> int:
-        return lib().oracle_steps(self._h)
+        return self._L.oracle_steps(self._h)
 
     def set_threads(self, n: int):
-        lib().oracle_set_threads(self._h, int(n))
+        self._L.oracle_set_threads(self._h, int(n))
 
     def omega(self, p: int) -> np.ndarray:
         out = np.zeros(49)
-        lib().oracle_omega(self._h, p, _dp(out))
+        self._L.oracle_omega(self._h, p, _dp(out))
         return out.reshape(7, 7)
 
     def tau(self, p: int) -> np.ndarray:
         out = np.zeros(9)
-        lib().oracle_tau(self._h, p, _dp(out))
+        self._L.oracle_tau(self._h, p, _dp(out))
         return out.reshape(3, 3)
 
     def set_bc(self, grad_axis: int, t_hot: float = 1.0, t_cold: float = 0.0, sides=(PERIODIC, PERIODIC, PERIODIC)):
         arr = (ctypes.c_int * 3)(*[int(s) for s in sides])
-        if lib().oracle_set_bc(self._h, int(grad_axis), float(t_hot), float(t_cold), arr):
+        if self._L.oracle_set_bc(self._h, int(grad_axis), float(t_hot), float(t_cold), arr):
             raise ValueError("bad boundary specification")
         self.grad_axis, self.t_hot, self.t_cold = int(grad_axis), float(t_hot), float(t_cold)
 
     def set_side_flux(self, axis: int, q_lo: float, q_hi: float):
         """Heat flux into the cell through the two faces of an adiabatic axis
         (Eq. 24; physical units of k times temperature per voxel)."""
-        if lib().oracle_set_side_flux(self._h, int(axis), float(q_lo), float(q_hi)):
+        if self._L.oracle_set_side_flux(self._h, int(axis), float(q_lo), float(q_hi)):
             raise ValueError("side flux needs an adiabatic axis")
 
     def init(self, T0=None, flux: bool = False):
@@ -150,33 +182,33 @@ class Oracle:
         central differences (see oracle_init_flux)."""
         if T0 is None:
             assert not flux, "a flux start needs a field"
-            lib().oracle_init(self._h, None)
+            self._L.oracle_init(self._h, None)
         else:
             t = np.ascontiguousarray(T0, dtype=np.float64).reshape(-1)
             assert t.size == self.n
             if flux:
-                lib().oracle_init_flux(self._h, _dp(t))
+                self._L.oracle_init_flux(self._h, _dp(t))
             else:
-                lib().oracle_init(self._h, _dp(t))
+                self._L.oracle_init(self._h, _dp(t))
 
     def collide_node(self, p: int, f7) -> np.ndarray:
         fin = np.ascontiguousarray(f7, dtype=np.float64)
         out = np.zeros(7)
-        lib().oracle_collide_node(self._h, int(p), _dp(fin), _dp(out))
+        self._L.oracle_collide_node(self._h, int(p), _dp(fin), _dp(out))
         return out
 
     def step(self, n: int = 1):
-        lib().oracle_step(self._h, int(n))
+        self._L.oracle_step(self._h, int(n))
 
     def temperature(self) -> np.ndarray:
         out = np.zeros(self.n)
-        lib().oracle_temperature(self._h, _dp(out))
+        self._L.oracle_temperature(self._h, _dp(out))
         return out.reshape(self.shape)
 
     def flux(self):
         q = np.zeros(3 * self.n)
         g = np.zeros(3 * self.n)
-        lib().oracle_flux(self._h, _dp(q), _dp(g))
+        self._L.oracle_flux(self._h, _dp(q), _dp(g))
         return q.reshape((3,) + self.shape), g.reshape((3,) + self.shape)
 
     @staticmethod
@@ -192,29 +224,29 @@ class Oracle:
 
     def keff(self) -> dict:
         out = np.zeros(7)
-        lib().oracle_keff(self._h, _dp(out))
+        self._L.oracle_keff(self._h, _dp(out))
         return self._kdict(out, self.steps)
 
     def solve(self, tol: float, kind: int = TOL_MAXDT, max_steps: int = 10**7, check_every: int = 1) -> dict:
         out = np.zeros(7)
-        rc = lib().oracle_solve(self._h, float(tol), int(kind), int(max_steps), int(check_every), _dp(out))
+        rc = self._L.oracle_solve(self._h, float(tol), int(kind), int(max_steps), int(check_every), _dp(out))
         if rc < 0:
             raise FloatingPointError("oracle state became non-finite")
         return self._kdict(out, self.steps, bool(rc))
 
     def get_f(self) -> np.ndarray:
         out = np.zeros(7 * self.n)
-        lib().oracle_get_f(self._h, _dp(out))
+        self._L.oracle_get_f(self._h, _dp(out))
         return out.reshape((7,) + self.shape)
 
     def set_f(self, f):
         f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
         assert f.size == 7 * self.n
-        lib().oracle_set_f(self._h, _dp(f))
+        self._L.oracle_set_f(self._h, _dp(f))
 
     def last_fluxes(self):
         out = np.zeros(3)
-        lib().oracle_last_fluxes(self._h, _dp(out))
+        self._L.oracle_last_fluxes(self._h, _dp(out))
         return dict(phi_hot=out[0], phi_cold=out[1], resid=out[2])
 
 

@@ -111,6 +111,7 @@ def load():
         "mrtlbm_step": (I, [P, LL]),
         "mrtlbm_solve": (I, [P, D, I, LL, I, RP]),
         "mrtlbm_solve_noalloc": (I, [P, D, I, LL, I, RP]),
+        "mrtlbm_stream_copy": (I, [P, P, LL, I, I, P]),
         "mrtlbm_keff": (I, [P, RP]),
         "mrtlbm_temperature": (I, [P, P]),
         "mrtlbm_flux": (I, [P, P]),

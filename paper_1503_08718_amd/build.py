@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmrtlbm.so")
 ARCH = os.environ.get("MRTLBM_ARCH", "gfx950")
 
-SOURCES = ["lbm_kernels.hip", "api.cpp", "batch_kernels.hip", "batch.cpp", "nn_kernels.hip", "nn_api.cpp", "noalloc.hip"]
+SOURCES = ["lbm_kernels.hip", "api.cpp", "batch_kernels.hip", "batch.cpp", "nn_kernels.hip", "nn_api.cpp", "noalloc.hip", "calib.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}",

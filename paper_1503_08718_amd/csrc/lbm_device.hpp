@@ -777,22 +777,32 @@ __device__ __forceinline__ void collide_store_pop32(const Cell<float> &c, const 
     }
 }
 
-template <typename real, int VEC, int MODE, int NT = 0, int STORAGE = 0>
+// One node update: pull, then `between()` (the single-cell step kernel
+// finishes staging the phase table in LDS there, so that the state loads are
+// already in flight while it waits at the barrier), then collide and store.
+struct NoOp {
+    __device__ void operator()() const {}
+};
+
+template <typename real, int VEC, int MODE, int NT = 0, int STORAGE = 0, typename Between = NoOp>
 __device__ __forceinline__ void node_update(const Cell<real> &c, const real *__restrict__ tab, int xv, int y, int z,
                                             bool active, const XLink &xl, Acc &acc, real *__restrict__ qout,
-                                            real qscale) {
+                                            real qscale, const Between &between = Between()) {
     if constexpr (STORAGE == 1 && sizeof(real) == 4) {
         PulledX<VEC, MODE> P;
         pull_mom_exact<VEC, MODE, NT>(c, xv, y, z, xl, P);
+        between();
         collide_store_exact<VEC, MODE, NT>(c, tab, xv, y, z, active, P, acc, qout, qscale);
     } else if constexpr ((STORAGE == 0 || STORAGE == 2) && sizeof(real) == 4) {
         Pulled<float, VEC> P;
         pull_dist<float, VEC, MODE, NT>(c, xv, y, z, xl, P);
+        between();
         collide_store_pop32<VEC, MODE, NT, STORAGE == 2>(c, tab, xv, y, z, active, P, acc, qout, qscale);
     } else {
         Pulled<real, VEC> P;
         if constexpr (STORAGE == 1) pull_mom<real, VEC, MODE, NT>(c, xv, y, z, xl, P);
         else pull_dist<real, VEC, MODE, NT>(c, xv, y, z, xl, P);
+        between();
         collide_store<real, VEC, MODE, NT, STORAGE>(c, tab, xv, y, z, active, P, acc, qout, qscale);
     }
 }
@@ -801,6 +811,32 @@ template <typename real>
 __device__ __forceinline__ void load_table(const Cell<real> &c, real *tab) {
     const int n = c.nphase * TABW;
     for (int i = threadIdx.y * blockDim.x + threadIdx.x; i < n; i += blockDim.x * blockDim.y) tab[i] = c.tab[i];
+    __syncthreads();
+}
+
+// The phase table staged in two halves: the first value of each thread is
+// read into a register before the state loads are issued, and written to
+// LDS (with the rest of the table, when it has more entries than the block
+// has threads) after them.
+template <typename real>
+struct TablePrefetch {
+    real v;
+};
+
+template <typename real>
+__device__ __forceinline__ TablePrefetch<real> table_prefetch(const Cell<real> &c) {
+    const int i = threadIdx.y * blockDim.x + threadIdx.x;
+    TablePrefetch<real> t;
+    t.v = (i < c.nphase * TABW) ? c.tab[i] : real(0);
+    return t;
+}
+
+template <typename real>
+__device__ __forceinline__ void table_commit(const Cell<real> &c, real *tab, const TablePrefetch<real> &t) {
+    const int n = c.nphase * TABW, nt = blockDim.x * blockDim.y;
+    const int i0 = threadIdx.y * blockDim.x + threadIdx.x;
+    if (i0 < n) tab[i0] = t.v;
+    for (int i = i0 + nt; i < n; i += nt) tab[i] = c.tab[i];
     __syncthreads();
 }
 

@@ -76,7 +76,7 @@ template <typename real, int VEC, int NT, int ST, int MAP>
 __global__ void __launch_bounds__(256) k_step(Cell<real> c) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     real *tab = reinterpret_cast<real *>(smem_raw);
-    load_table(c, tab);
+    const TablePrefetch<real> tp = table_prefetch(c);
     int bxi, byi, bzi;
     block_coords<MAP>(bxi, byi, bzi);
     const int tx = threadIdx.x, bx = blockDim.x;
@@ -88,7 +88,7 @@ __global__ void __launch_bounds__(256) k_step(Cell<real> c) {
     y = min(y, c.ny - 1);
     Acc dummy;
     node_update<real, VEC, 0, NT, ST>(c, tab, xv, y, z, active, chunk_links<VEC>(c, xv, tx, bx), dummy, nullptr,
-                                      real(0));
+                                      real(0), [&]() { table_commit(c, tab, tp); });
 }
 
 // Observables (and optionally the step): the grid covers x and y like the
