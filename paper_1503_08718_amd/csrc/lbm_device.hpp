@@ -550,8 +550,12 @@ __device__ __forceinline__ void pull_mom_exact(const Cell<float> &c, int xv, int
     const int zp = zhi ? (c.per[2] ? 0 : z) : z + 1;
     const bool wym = ylo && !c.per[1], wyp = yhi && !c.per[1], wzm = zlo && !c.per[2], wzp = zhi && !c.per[2];
     constexpr bool NL = (NT & 1) != 0;
+    // jhat_x/2 of a node is read only by that node (its x neighbours take it
+    // by lane exchange), never again by another block: always streamed
+    // non-temporally, unlike T, jhat_y and jhat_z, which the y and z
+    // neighbours re-read from L2
     Vec<float, VEC> Tc = vload<float, VEC, NL>(sT + base);
-    Vec<float, VEC> Xc = vload<float, VEC, NL>(sX + base);
+    Vec<float, VEC> Xc = vload<float, VEC, true>(sX + base);
     const long long rym = ((long long)z * ny + ym) * nx + x0, ryp = ((long long)z * ny + yp) * nx + x0;
     const long long rzm = ((long long)zm * ny + y) * nx + x0, rzp = ((long long)zp * ny + y) * nx + x0;
     Vec<float, VEC> Tym = vload<float, VEC, NL>(sT + rym), Yym = vload<float, VEC, NL>(sY + rym);
@@ -777,32 +781,34 @@ __device__ __forceinline__ void collide_store_pop32(const Cell<float> &c, const 
     }
 }
 
-// One node update: pull, then `between()` (the single-cell step kernel
-// finishes staging the phase table in LDS there, so that the state loads are
-// already in flight while it waits at the barrier), then collide and store.
+// One node update: pull, then `between(tab)` (the single-cell step kernel
+// finishes staging the phase table in LDS there and may point tab at it, so
+// that the state loads are already in flight meanwhile), then collide and
+// store.
 struct NoOp {
-    __device__ void operator()() const {}
+    template <typename T>
+    __device__ void operator()(const T *&) const {}
 };
 
 template <typename real, int VEC, int MODE, int NT = 0, int STORAGE = 0, typename Between = NoOp>
-__device__ __forceinline__ void node_update(const Cell<real> &c, const real *__restrict__ tab, int xv, int y, int z,
+__device__ __forceinline__ void node_update(const Cell<real> &c, const real *tab, int xv, int y, int z,
                                             bool active, const XLink &xl, Acc &acc, real *__restrict__ qout,
                                             real qscale, const Between &between = Between()) {
     if constexpr (STORAGE == 1 && sizeof(real) == 4) {
         PulledX<VEC, MODE> P;
         pull_mom_exact<VEC, MODE, NT>(c, xv, y, z, xl, P);
-        between();
+        between(tab);
         collide_store_exact<VEC, MODE, NT>(c, tab, xv, y, z, active, P, acc, qout, qscale);
     } else if constexpr ((STORAGE == 0 || STORAGE == 2) && sizeof(real) == 4) {
         Pulled<float, VEC> P;
         pull_dist<float, VEC, MODE, NT>(c, xv, y, z, xl, P);
-        between();
+        between(tab);
         collide_store_pop32<VEC, MODE, NT, STORAGE == 2>(c, tab, xv, y, z, active, P, acc, qout, qscale);
     } else {
         Pulled<real, VEC> P;
         if constexpr (STORAGE == 1) pull_mom<real, VEC, MODE, NT>(c, xv, y, z, xl, P);
         else pull_dist<real, VEC, MODE, NT>(c, xv, y, z, xl, P);
-        between();
+        between(tab);
         collide_store<real, VEC, MODE, NT, STORAGE>(c, tab, xv, y, z, active, P, acc, qout, qscale);
     }
 }

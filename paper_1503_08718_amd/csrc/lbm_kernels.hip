@@ -76,7 +76,12 @@ template <typename real, int VEC, int NT, int ST, int MAP>
 __global__ void __launch_bounds__(256) k_step(Cell<real> c) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     real *tab = reinterpret_cast<real *>(smem_raw);
-    const TablePrefetch<real> tp = table_prefetch(c);
+    // moment storage: the state loads go out before the table is staged
+    // (measured faster there; population storage stages the table first)
+    constexpr bool LATE_TABLE = (ST == 1);
+    TablePrefetch<real> tp;
+    if constexpr (LATE_TABLE) tp = table_prefetch(c);
+    else load_table(c, tab);
     int bxi, byi, bzi;
     block_coords<MAP>(bxi, byi, bzi);
     const int tx = threadIdx.x, bx = blockDim.x;
@@ -88,7 +93,9 @@ __global__ void __launch_bounds__(256) k_step(Cell<real> c) {
     y = min(y, c.ny - 1);
     Acc dummy;
     node_update<real, VEC, 0, NT, ST>(c, tab, xv, y, z, active, chunk_links<VEC>(c, xv, tx, bx), dummy, nullptr,
-                                      real(0), [&]() { table_commit(c, tab, tp); });
+                                      real(0), [&](const real *&) {
+                                          if constexpr (LATE_TABLE) table_commit(c, tab, tp);
+                                      });
 }
 
 // Observables (and optionally the step): the grid covers x and y like the

@@ -96,6 +96,7 @@ class Net:
             for d, ref in ((self.mw, self.w32), (self.vw, self.w32), (self.mb, self.b32), (self.vb, self.b32)):
                 d[name] = torch.zeros_like(ref[name])
         self.t = 0
+        self.rng_state = None  # batch-order generator state of train(), kept in checkpoints
         self._alloc(batch)
 
     # -- buffers -------------------------------------------------------------
@@ -259,8 +260,15 @@ class Net:
 
     # -- persistence -----------------------------------------------------------
     def state_dict(self):
-        return {"w": {k: v.cpu() for k, v in self.w32.items()}, "b": {k: v.cpu() for k, v in self.b32.items()},
-                "n": self.n, "t": self.t}
+        """Everything training needs to continue bit for bit: FP32 master
+        weights and biases, Adam's moments and step count, and the state of
+        the batch-order generator (set by train())."""
+        cpu = lambda d: {k: v.cpu() for k, v in d.items()}  # noqa: E731
+        sd = {"w": cpu(self.w32), "b": cpu(self.b32), "n": self.n, "t": self.t,
+              "adam": {"mw": cpu(self.mw), "vw": cpu(self.vw), "mb": cpu(self.mb), "vb": cpu(self.vb)}}
+        if self.rng_state is not None:
+            sd["rng"] = self.rng_state
+        return sd
 
     def load_state_dict(self, sd):
         for name, _, _, _ in LAYERS:
@@ -268,7 +276,11 @@ class Net:
             self.b32[name].copy_(sd["b"][name].to(self.dev))
             check(self.L.mrtlbm_nn_to_bf16(_p(self.w32[name]), self.w32[name].numel(), _p(self.wbf[name]),
                                            self.stream))
+            if "adam" in sd:
+                for key, d in (("mw", self.mw), ("vw", self.vw), ("mb", self.mb), ("vb", self.vb)):
+                    d[name].copy_(sd["adam"][key][name].to(self.dev))
         self.t = int(sd.get("t", 0))
+        self.rng_state = sd.get("rng")
 
     def save(self, path):
         torch.save(self.state_dict(), path)
@@ -423,28 +435,38 @@ def iteration_flops(net: Net) -> float:
     return sum(f * (2 if name == "c00" else 3) for name, f in layer_flops(net).items())
 
 
-def train(net: Net, data, iters=2000, lr=1e-3, seed=0, log=print, log_every=100):
+def train(net: Net, data, iters=2000, lr=1e-3, seed=0, log=print, log_every=100, horizon=None):
+    """Adam iterations net.t + 1 .. iters, the learning rate decaying from lr
+    to lr / 10 over `horizon` iterations (default iters).  A network loaded
+    from a checkpoint continues where it stopped, with the same batches and
+    learning rates when given the same horizon."""
+    horizon = horizon or iters
     phases, feats, targets = data
     S = phases.shape[0]
     rng = np.random.default_rng(seed)
+    if net.rng_state is not None:
+        rng.bit_generator.state = net.rng_state
     nv = net.n ** 3
     losses = []
     t0 = time.perf_counter()
-    for it in range(1, iters + 1):
+    first = net.t + 1
+    for it in range(first, iters + 1):
         idx = rng.choice(S, size=net.batch, replace=False)
+        net.rng_state = rng.bit_generator.state
         for b, i in enumerate(idx):
             net.set_input(b, phases[i], feats[i])
             net.target[b * nv:(b + 1) * nv].copy_(targets[i])
         net.forward()
         net.loss_and_grad()
         net.backward()
-        cur_lr = lr * (0.1 ** (it / iters))  # exponential decay to lr / 10
+        cur_lr = lr * (0.1 ** (it / horizon))  # exponential decay to lr / 10
         net.adam(lr=cur_lr)
         if it % log_every == 0 or it == iters:
             loss = float(net.loss.item())
             losses.append((it, loss))
             dt = time.perf_counter() - t0
-            log(f"train it {it}: loss {loss:.3e}  ({dt:.1f} s, {iteration_flops(net) * it / dt / 1e12:.2f} TFLOP/s)")
+            log(f"train it {it}: loss {loss:.3e}  ({dt:.1f} s, "
+                f"{iteration_flops(net) * (it - first + 1) / dt / 1e12:.2f} TFLOP/s)")
     return losses
 
 

@@ -185,7 +185,7 @@ def _q(a):
     return torch.tensor(np.asarray(a, np.float32)).to(torch.bfloat16).double().numpy()
 
 
-def _oracle_net(x, W, B, target):
+def _oracle_net(x, W, B, target, keep=False):
     """FP64 forward/backward of the warm-start network with the same weights.
     Every tensor the GPU stores in BF16 is rounded to BF16 at the same point,
     so that both sides take the same ReLU decisions."""
@@ -253,14 +253,35 @@ def _oracle_net(x, W, B, target):
     g_e0 = _q(_q(C.pool2_backward(g_p1)) + g_s0)
     g_a00 = back("c01", f["a00"], f["e0"], g_e0)
     back("c00", x, f["a00"], g_a00)
-    return loss, out, grads
+    return (loss, out, grads, f) if keep else (loss, out, grads)
 
 
-def test_whole_network_forward_and_gradients(env):
+# every layer of the network: (input activation, output activation, upstream
+# gradient, where its input gradient goes), as Net.forward / Net.backward
+# store them
+TEACHER = {
+    "c00": ("x", "a00", ("grad", "a00"), None, 0),
+    "c01": ("a00", "e0", ("grad", "e0"), "a00", 0),
+    "c10": ("p1", "a10", ("grad", "a10"), "p1", 1),
+    "c11": ("a10", "e1", ("grad", "e1"), "a10", 1),
+    "c20": ("p2", "a20", ("grad", "a20"), "p2", 2),
+    "c21": ("a20", "e2", ("grad", "e2"), "a20", 2),
+    "c30": ("p3", "a30", ("grad", "a30"), "p3", 3),
+    "c31": ("a30", "e3", ("grad", "e3"), "a30", 3),
+    "c22": ("u2", "b2", ("grad", "s2"), "u2", 2),
+    "c23": ("s2", "d2", ("grad", "d2"), "s2", 2),
+    "c12": ("u1", "b1", ("grad", "s1"), "u1", 1),
+    "c13": ("s1", "d1", ("grad", "d1"), "s1", 1),
+    "c02": ("u0", "b0", ("grad", "s0"), "u0", 0),
+    "c03": ("s0", "d0", ("grad", "d0"), "s0", 0),
+    "c04": ("d0", None, ("act", "dout"), "d0", 0),
+}
+
+
+def _trained_net_pass(env, n=32):
     L, torch = env
     from paper_1503_08718_amd import warmstart as ws
 
-    n = 32
     net = ws.Net(n=n, batch=1, seed=3)
     rng = np.random.default_rng(11)
     xd, x = bf(torch, np.concatenate([rng.uniform(-1, 1, (n ** 3, 7)), np.zeros((n ** 3, 1))], axis=1))
@@ -270,27 +291,94 @@ def test_whole_network_forward_and_gradients(env):
     net.forward()
     net.loss_and_grad()
     net.backward()
+    torch.cuda.synchronize()
     W, B = {}, {}
     for name, cin, cout, _ in ws.LAYERS:
         wq = net.wbf[name].float().cpu().numpy().astype(np.float64)
         W[name] = wq[:, :27 * cin].reshape(cout, 3, 3, 3, cin)
         B[name] = net.b32[name].cpu().numpy().astype(np.float64)
-    loss, out, grads = _oracle_net(x.reshape(1, n, n, n, 8), W, B, tgt.astype(np.float64))
+    return net, ws, x, tgt, W, B
+
+
+def test_every_layer_teacher_forced(env):
+    """Each of the 15 layers of one forward and backward pass at 32^3, fed
+    with the GPU's own stored BF16 input activation and upstream gradient:
+    the FP64 oracle's output, input gradient (BF16 on the GPU: relative L2
+    <= 1e-2, cosine >= 0.999) and weight and bias gradients (FP32 on the GPU
+    from exact BF16 operands: relative L2 <= 1e-4) -- the per-kernel bars,
+    layer by layer, so that an indexing or adjoint fault in any one layer
+    cannot hide behind the BF16 rounding of the layers before it."""
+    L, torch = env
+    net, ws, _, _, W, B = _trained_net_pass(env)
+    n = net.n
+    circ = (False, True, True)
+
+    def host(t, lv, c):
+        d = n >> lv
+        return t.float().cpu().numpy().astype(np.float64).reshape(1, d, d, d, -1)[..., :c]
+
+    report = []
+    for name, cin, cout, relu in ws.LAYERS:
+        src, dst, (kind, gname), dxname, lv = TEACHER[name]
+        xin = host(net.act[src], lv, cin)
+        dy = host((net.grad if kind == "grad" else net.act)[gname], lv, cout)
+        y_or = C.conv3d(xin, W[name], B[name], circ)
+        if relu:
+            y_gpu = host(net.act[dst], lv, cout)
+            y_ref = _q(C.relu(y_or))
+            assert rel_l2(y_gpu, y_ref) <= 1e-2 and cosine(y_gpu, y_ref) >= 0.999, (name, "forward")
+            dpre = _q(dy * (y_gpu > 0))  # the GPU's own ReLU decisions
+        else:
+            out = net.out.cpu().numpy().astype(np.float64).reshape(1, n, n, n, cout)
+            assert rel_l2(out, y_or) <= 1e-4, (name, "forward")
+            dpre = dy
+        dx, dw, db = C.conv3d_backward(xin, W[name], dpre, circ)
+        gw = net.gw[name].cpu().numpy()[:, :27 * cin].astype(np.float64)
+        gb = net.gb[name].cpu().numpy().astype(np.float64)
+        rw, rb = rel_l2(gw, dw.reshape(cout, -1)), rel_l2(gb, db)
+        line = [name, rw, rb]
+        assert rw <= 1e-4 and rb <= 1e-4, (name, rw, rb)
+        if dxname is not None:
+            g_dx = host(net.grad[dxname], lv, cin)
+            rx, cx = rel_l2(g_dx, dx), cosine(g_dx, dx)
+            line += [rx, cx]
+            assert rx <= 1e-2 and cx >= 0.999, (name, "input gradient", rx, cx)
+        report.append(line)
+    print("layer: weight-grad rel L2, bias-grad rel L2, [input-grad rel L2, cosine]")
+    for line in report:
+        print(" ".join(f"{v:.3e}" if isinstance(v, float) else v for v in line))
+
+
+def test_whole_network_forward_and_gradients(env):
+    """The whole pass against an FP64 oracle that runs the network on its own,
+    rounding to BF16 wherever the GPU stores.  The forward output and the
+    loss agree closely; deep in the backward pass, the two sides' ReLU
+    decisions part where a pre-activation lies within BF16 rounding of zero,
+    so the end-to-end weight gradients are held only to a direction (cosine
+    > 0.99); each layer meets the per-kernel bars in the teacher-forced test
+    above.  The share of ReLU decisions that differ is measured and bounded."""
+    L, torch = env
+    net, ws, x, tgt, W, B = _trained_net_pass(env)
+    n = net.n
+    loss, out, grads, fwd = _oracle_net(x.reshape(1, n, n, n, 8), W, B, tgt.astype(np.float64), keep=True)
     got_out = net.out.cpu().numpy()[:, 0]
     assert cosine(got_out, out[..., 0].ravel()) > 0.999
     assert abs(net.loss.item() - loss) < 0.02 * loss
-    report = {}
+    flips, total = 0, 0
+    for name, cin, cout, relu in ws.LAYERS:
+        if not relu:
+            continue
+        src, dst, _, _, lv = TEACHER[name]
+        d = n >> lv
+        yg = net.act[dst].float().cpu().numpy().reshape(1, d, d, d, -1)[..., :cout] > 0
+        flips += int(np.count_nonzero(yg != (fwd[dst] > 0)))
+        total += yg.size
+    print(f"ReLU decisions that differ: {flips} of {total}")
+    assert flips <= 1e-2 * total
     for name, cin, cout, _ in ws.LAYERS:
         gw = net.gw[name].cpu().numpy()[:, :27 * cin]
         rw = grads[name][0].reshape(cout, -1)
-        report[name] = (cosine(gw, rw), rel_l2(gw, rw), rel_l2(net.gb[name].cpu().numpy(), grads[name][1]))
-    print("layer: weight-gradient cosine, rel L2, bias-gradient rel L2")
-    for name, v in report.items():
-        print(f"{name}: {v[0]:.6f} {v[1]:.3e} {v[2]:.3e}")
-    # through fifteen layers of BF16 storage the per-layer weight gradients
-    # keep cosine >= 0.99 (every single kernel meets 0.999 on its own)
-    for name, (cos, rl2, rlb) in report.items():
-        assert cos > 0.99 and rl2 < 0.2, (name, cos, rl2)
+        assert cosine(gw, rw) > 0.99, name
 
 
 @pytest.mark.parametrize("coarse", [(10, 12, 20), (5, 6, 10), (8, 8, 8), (16, 16, 16), (4, 12, 7)],
@@ -367,3 +455,33 @@ def test_feature_table_spacing(env):
     bad = k6.copy()
     bad[1, 3] = 10.0 * np.sqrt(bad[1, 0] * bad[1, 1])
     assert table(bad, sp)[0] == -2  # E_TENSOR
+
+
+def test_training_resumes_bit_for_bit(env, tmp_path):
+    """A checkpoint holds the master weights, Adam's moments and step count
+    and the batch-order generator: 3 iterations, save, load into a fresh
+    network, 3 more, equal 6 iterations straight through, bit for bit."""
+    L, torch = env
+    from paper_1503_08718_amd import warmstart as ws
+
+    n, S = 16, 5
+    g = torch.Generator().manual_seed(4)
+    phases = torch.randint(0, 3, (S, n ** 3), generator=g, dtype=torch.uint8).cuda()
+    feats = (torch.rand((S, 3, 6), generator=g) - 0.5).cuda()
+    targets = (torch.rand((S, n ** 3), generator=g) * 0.2).cuda()
+    data = (phases, feats, targets)
+    quiet = lambda *a, **k: None  # noqa: E731
+    a = ws.Net(n=n, batch=2, seed=5)
+    ws.train(a, data, iters=6, seed=9, log=quiet)
+    b = ws.Net(n=n, batch=2, seed=5)
+    ws.train(b, data, iters=3, seed=9, log=quiet, horizon=6)
+    path = str(tmp_path / "ckpt.pt")
+    b.save(path)
+    c = ws.Net.from_file(path, batch=2)
+    assert c.t == 3 and c.rng_state is not None
+    ws.train(c, data, iters=6, seed=9, log=quiet)
+    torch.cuda.synchronize()
+    for name, _, _, _ in ws.LAYERS:
+        assert torch.equal(a.w32[name], c.w32[name]), name
+        assert torch.equal(a.b32[name], c.b32[name]), name
+        assert torch.equal(a.vw[name], c.vw[name]), name
