@@ -27,7 +27,9 @@ bool batch_layout(mrtlbm_medium *const *cells, int n, BatchLayout *L) {
     long long mt = 0;
     for (int i = 0; i < n; i++) {
         if (!cells[i]) return false;
-        mt += (long long)cells[i]->nz * cells[i]->ny;
+        // rows of up to 64 threads' worth of nodes per tile at the least
+        // (vec 1, 64 threads): enough for every shape the batch may take
+        mt += (long long)cells[i]->nz * cells[i]->ny * ((cells[i]->nx + 63) / 64);
     }
     mt += 8;  // room to pad the table to a multiple of 8 (XCD-aware order)
     if (mt > (1LL << 31) - 1) return false;
@@ -78,17 +80,27 @@ mrtlbm_status upload_cells(BatchRun &B) {
     return e == hipSuccess ? MRTLBM_OK : hip_fail(e, "batch cell table upload");
 }
 
-// tiles of the active cells (contiguous per cell) and per-cell tile ranges
+// tiles of the active cells (contiguous per cell) and per-cell tile ranges.
+// A tile is (cell, z, y0, rows): `rows` whole rows from y0, packed over the
+// block's threads; a row longer than the block is cut into x-chunks of one
+// tile each, (cell, z, y, -1 - chunk).
 mrtlbm_status upload_tiles(BatchRun &B) {
     std::vector<int4> tiles;
     std::vector<int> start;
     for (int a : B.active) {
         const mrtlbm_medium *m = B.cells[a];
         const int nxv = m->nx / B.vec;
-        const int rows = B.threads / nxv;
         start.push_back((int)tiles.size());
-        for (int z = 0; z < m->nz; z++)
-            for (int y0 = 0; y0 < m->ny; y0 += rows) tiles.push_back(int4{a, z, y0, std::min(rows, m->ny - y0)});
+        if (nxv <= B.threads) {
+            const int rows = B.threads / nxv;
+            for (int z = 0; z < m->nz; z++)
+                for (int y0 = 0; y0 < m->ny; y0 += rows) tiles.push_back(int4{a, z, y0, std::min(rows, m->ny - y0)});
+        } else {
+            const int chunks = (nxv + B.threads - 1) / B.threads;
+            for (int z = 0; z < m->nz; z++)
+                for (int y = 0; y < m->ny; y++)
+                    for (int k = 0; k < chunks; k++) tiles.push_back(int4{a, z, y, -1 - k});
+        }
     }
     start.push_back((int)tiles.size());
     B.chunk = 0;
@@ -210,11 +222,8 @@ static mrtlbm_status prepare(BatchRun &B, mrtlbm_medium *const *cells, int n, vo
             if (cells[j] == m) return fail(MRTLBM_E_ARG, "cell %d listed twice", i);
     }
     if (vec < 1) vec = 1;
-    for (int i = 0; i < n; i++)
-        if (cells[i]->nx / vec > threads) threads = 256;
-    for (int i = 0; i < n; i++)
-        if (cells[i]->nx / vec > threads)
-            return fail(MRTLBM_E_ARG, "cell %d: rows of %d nodes are too long to batch", i, cells[i]->nx);
+    // rows longer than a tile's threads are cut into x-chunks (one tile per
+    // chunk of one row)
     B.cells = cells;
     B.n = n;
     B.vec = vec;
@@ -307,7 +316,7 @@ extern "C" mrtlbm_status mrtlbm_batch_autotune(mrtlbm_medium *const *cells, int 
                 for (int map : {0, 1}) {
                     bool ok = true;
                     for (int i = 0; i < n && ok; i++)
-                        ok = cells[i]->nx % vec == 0 && cells[i]->nx / vec <= threads;
+                        ok = cells[i]->nx % vec == 0;
                     if (!ok) continue;
                     B.vec = vec; B.threads = threads; B.nt = nt; B.map = map;
                     double ms = 0.0;

@@ -26,7 +26,8 @@ __device__ __forceinline__ XLink packed_links(int xv, int nxv) {
     return xl;
 }
 
-// tile = (cell, z-plane, first row y0, number of rows).  chunk > 0: the
+// tile = (cell, z-plane, first row y0, number of rows), or for rows longer
+// than the block (cell, z-plane, row, -1 - x-chunk).  chunk > 0: the
 // table holds 8 * chunk tiles and block b takes tile (b % 8) * chunk + b / 8,
 // so that each XCD (blocks go to the 8 XCDs round robin) sweeps one
 // contiguous eighth of the table and finds the neighbouring rows and planes
@@ -46,11 +47,19 @@ __global__ void __launch_bounds__(256) k_batch(const Cell<real> *__restrict__ ce
     }
     load_table(c, tab);
     const int t = threadIdx.x;
-    const int rows = blockDim.x / c.nxv;
-    const int r = t / c.nxv;
-    int xv = t - r * c.nxv;
-    int y = tile.z + r;
-    const bool active = (r < rows) && (r < tile.w) && (y < c.ny);
+    int xv, y;
+    bool active;
+    if (tile.w >= 0) {  // tile.w whole rows from tile.z
+        const int rows = blockDim.x / c.nxv;
+        const int r = t / c.nxv;
+        xv = t - r * c.nxv;
+        y = tile.z + r;
+        active = (r < rows) && (r < tile.w) && (y < c.ny);
+    } else {  // x-chunk -1 - tile.w of row tile.z
+        xv = (-1 - tile.w) * (int)blockDim.x + t;
+        y = tile.z;
+        active = xv < c.nxv;
+    }
     xv = min(xv, c.nxv - 1);
     y = min(y, c.ny - 1);
     const int z = tile.y;

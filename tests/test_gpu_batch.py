@@ -191,3 +191,39 @@ def test_batch_of_degenerate_cells(api, prec):
         assert torch.equal(b.state_get(), a.state_get())
         for key in ("keff_hot", "keff_cold", "keff_vol"):
             assert abs(r[key] - ra[key]) <= 1e-12 * max(1.0, abs(ra[key])), key
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batch_rows_longer_than_a_block(api, prec):
+    """Rows of more nodes than a tile has threads are cut into x-chunks, one
+    tile each; such a cell batched with short-row cells evolves bit for bit
+    like the same cell stepped alone, and (FP64) like the oracle."""
+    import torch
+
+    specs = [((300, 3, 2), 0, ("periodic", "periodic", "adiabatic")),   # 300 > 256 threads at vec 1
+             ((1030, 2, 2), 1, ("periodic", "periodic", "periodic")),   # periodic x across 5 chunks
+             ((13, 6, 5), 2, ("adiabatic", "periodic", "periodic"))]
+
+    def make():
+        out = []
+        for i, (shape, g, sides) in enumerate(specs):
+            m = w.random_medium(90 + i, *shape, 3)
+            T0 = np.random.default_rng(90 + i).uniform(0, 1, m.phase.shape)
+            out.append((m, g, sides, T0, api.Medium(m.phase, m.k, precision=prec).set_bc(g, 1.0, 0.0, sides).init(T0)))
+        return out
+
+    batch, alone = make(), make()
+    batch[0][4].set_launch(1, 64, 1, 0, 1)  # 64 threads per tile: 300 nodes = 5 chunks
+    res, st = api.batch_solve([b[4] for b in batch], tol=1e-30, kind="keff", max_steps=200, check_every=100)
+    assert st == "NOT_CONVERGED"
+    for (m, g, sides, T0, b), (_, _, _, _, a), r in zip(batch, alone, res):
+        ra = a.solve(1e-30, "keff", 200, check_every=100)
+        assert r["steps"] == ra["steps"] == 200
+        assert torch.equal(b.state_get(), a.state_get())
+        if prec == "f64":
+            o = Oracle(m.phase, m.k)
+            o.set_bc(g, 1.0, 0.0, [ORACLE_SIDES[s] for s in sides])
+            o.init(T0)
+            o.step(200)
+            to = o.temperature()
+            assert np.abs(b.temperature().cpu().numpy() - to).max() < 1e-12 * np.abs(to).max()

@@ -374,7 +374,7 @@ def test_whole_network_forward_and_gradients(env):
         flips += int(np.count_nonzero(yg != (fwd[dst] > 0)))
         total += yg.size
     print(f"ReLU decisions that differ: {flips} of {total}")
-    assert flips <= 1e-2 * total
+    assert flips <= 2e-3 * total  # measured: 1783 of 2768896 (6.4e-4)
     for name, cin, cout, _ in ws.LAYERS:
         gw = net.gw[name].cpu().numpy()[:, :27 * cin]
         rw = grads[name][0].reshape(cout, -1)
