@@ -299,7 +299,8 @@ size_t mrtlbm_batch_workspace_bytes(mrtlbm_medium *const *cells, int n);
 
 /*
  * Solve n initialised media together.  Every step is one kernel launch that
- * covers all still-active cells (a table of row tiles), and the steps between
+ * covers all still-active cells (a table of row tiles: whole rows packed over
+ * a tile's threads, or x-chunks of rows longer than that), and the steps between
  * checks are replayed as one hip graph; a cell leaves the table when its own
  * stop rule holds.  All cells must share the precision and the stream of
  * cells[0]; the step's shape (vec, bx * by threads per row tile, nt, map)
