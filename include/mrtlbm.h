@@ -163,7 +163,9 @@ mrtlbm_status mrtlbm_set_side_flux(mrtlbm_medium *m, int axis, double q_lo, doub
  * than 1 need population storage (E_ARG under moment storage, and
  * mrtlbm_set_storage(m, 1) then fails) and are not accepted by
  * mrtlbm_batch_solve.  The step then relaxes all six non-conserved moments of
- * Eq. 11 (7 populations per node).  The state stays valid. */
+ * Eq. 11 (7 populations per node); in FP32 the seven outputs are formed
+ * exactly in FP64 from the FP32 inputs and each is rounded to FP32 with the
+ * dither described at mrtlbm_set_storage.  The state stays valid. */
 mrtlbm_status mrtlbm_set_relaxation(mrtlbm_medium *m, double tau4, double tau5, double tau6);
 
 /* Relaxation scale: largest eigenvalue of tau - I/2 over all phases
