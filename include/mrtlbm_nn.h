@@ -54,7 +54,9 @@ mrtlbm_status mrtlbm_nn_conv3d_dgrad(const void *dout, int n, int d, int h, int 
 size_t mrtlbm_nn_wgrad_scratch_bytes(int n, int d, int h, int w, int cin, int cout);
 
 /* Weight and bias gradients: dw[co][k] = sum_v dout[v][co] in[v + off(tap)][ci]
- * ([cout][kpad], padding entries 0), db[co] = sum_v dout[v][co]; db may be NULL. */
+ * ([cout][kpad], padding entries 0), db[co] = sum_v dout[v][co]; db may be NULL.
+ * cout <= 128 (E_ARG otherwise).  Voxel chunks are staged through LDS and
+ * summed in a fixed order: the result does not depend on timing. */
 mrtlbm_status mrtlbm_nn_conv3d_wgrad(const void *in, const void *dout, int n, int d, int h, int w, int cin, int cout,
                                      int circ, float *scratch, float *dw, float *db, void *stream);
 

@@ -59,9 +59,8 @@ extern "C" mrtlbm_status mrtlbm_nn_conv3d_dgrad(const void *dout, int n, int d, 
 extern "C" size_t mrtlbm_nn_wgrad_scratch_bytes(int n, int d, int h, int w, int cin, int cout) {
     ConvGeom g;
     if (!geom(n, d, h, w, cin, cout, 0, &g)) return 0;
-    const size_t s = (size_t)nn_wgrad_splits(g);
-    const size_t a = s * (size_t)cout * g.kpad * sizeof(float);
-    const size_t b = s * (size_t)cout * sizeof(float);
+    const size_t a = (size_t)nn_wgrad_partials(g) * (size_t)cout * g.kpad * sizeof(float);
+    const size_t b = (size_t)nn_wgrad_splits(g) * (size_t)cout * sizeof(float);
     return a > b ? a : b;
 }
 
@@ -71,6 +70,7 @@ extern "C" mrtlbm_status mrtlbm_nn_conv3d_wgrad(const void *in, const void *dout
     ConvGeom g;
     if (!geom(n, d, h, w, cin, cout, circ, &g) || !in || !dout || !scratch || !dw)
         return fail(MRTLBM_E_ARG, "conv3d_wgrad: bad arguments");
+    if (cout > 128) return fail(MRTLBM_E_ARG, "conv3d_wgrad: cout %d > 128", cout);
     hipStream_t s = (hipStream_t)stream;
     const int splits = nn_wgrad_splits(g);
     hipError_t e = nn_conv_wgrad(in, dout, g, splits, scratch, dw, s);

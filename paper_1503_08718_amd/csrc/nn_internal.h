@@ -15,6 +15,7 @@ hipError_t nn_conv_fwd(const void *in, const void *w, const float *bias, const C
                        float *out_f32, hipStream_t s);
 hipError_t nn_weight_flip(const void *w, int cin, int cout, int kpad, int kpad_t, void *wt, hipStream_t s);
 int nn_wgrad_splits(const ConvGeom &g);
+int nn_wgrad_partials(const ConvGeom &g);
 hipError_t nn_conv_wgrad(const void *x, const void *dy, const ConvGeom &g, int splits, float *partials, float *dw,
                          hipStream_t s);
 hipError_t nn_bias_grad(const void *dy, long long nvox, int c, int splits, float *partials, float *db, hipStream_t s);

@@ -133,70 +133,155 @@ __global__ void k_weight_flip(const bf16 *__restrict__ w, int cin, int cout, int
     }
 }
 
-// weight gradient, split over voxels: partials[s][co][k] = sum over this
-// split's voxels of dy[v][co] * x[neighbour(v, tap)][ci].  One wave per block:
-// 16 output channels x 32 k (two 16-wide column tiles).
-__global__ void __launch_bounds__(64) k_conv_wgrad(const bf16 *__restrict__ x, const bf16 *__restrict__ dy, ConvGeom g,
-                                                   long long vox_per_split, float *__restrict__ partials) {
-    const int lane = threadIdx.x;
-    const int ktile = blockIdx.x, cotile = blockIdx.y, s = blockIdx.z;
+// Weight gradient through LDS.  dW[co][k] = sum_v dy[v][co] x[nb(v, tap(k))][ci(k)]
+// is a product with the voxels as its inner dimension, while both operands
+// sit channels-last in memory; each wave therefore stages, per chunk of 32
+// voxels, the chunk's dy and the x columns of the block's k-range into LDS
+// transposed (voxels contiguous, rows padded to 40 elements so that the
+// 16-byte operand reads of one MFMA hit 64 distinct banks), and feeds the
+// 16x16x32 MFMA from there: A = dy^T rows (output channels), B = x columns
+// (k).  Block: 4 waves, KT 32-wide k-tiles (KT * cout / 2 accumulator
+// registers); the waves take every fourth chunk of the block's voxel split,
+// their sums are added in a fixed order and the block writes one partial per
+// split, summed over the splits in a fixed order afterwards.
+constexpr int WG_ROW = 40;  // padded LDS row, in bf16
+
+template <int MT, int KT>
+__global__ void __launch_bounds__(256) k_conv_wgrad_lds(const bf16 *__restrict__ x, const bf16 *__restrict__ dy,
+                                                        ConvGeom g, long long vox_per_split,
+                                                        float *__restrict__ partials) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int cout = g.cout, cin = g.cin, K27 = 27 * g.cin;
+    // this wave's staging area: dy^T [cout][WG_ROW] then x^T [32 KT][WG_ROW]
+    bf16 *dyT = reinterpret_cast<bf16 *>(smem_raw) + (size_t)wave * (cout + 32 * KT) * WG_ROW;
+    bf16 *xT = dyT + (size_t)cout * WG_ROW;
+    const int kbase = blockIdx.x * 32 * KT;
+    const int s = blockIdx.y;
     const long long nvox = (long long)g.n * g.D * g.H * g.W;
-    const long long vb = s * vox_per_split;
-    const long long ve = min(nvox, vb + vox_per_split);
-    const int co = cotile * 16 + (lane & 15);
-    const int K27 = 27 * g.cin;
-    int kcol[2], tap[2], ci[2];
+    const long long vb = s * vox_per_split, ve = min(nvox, vb + vox_per_split);
+    f32x4 acc[MT][2 * KT];  // MT = cout / 16 row tiles
 #pragma unroll
-    for (int j = 0; j < 2; j++) {
-        kcol[j] = ktile * 32 + j * 16 + (lane & 15);
-        tap[j] = kcol[j] / g.cin;
-        ci[j] = kcol[j] - tap[j] * g.cin;
-    }
-    f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
-    for (long long v0 = vb; v0 < ve; v0 += 32) {
-        const long long vq = v0 + (lane >> 4) * 8;
-        bf16x8 a, b[2];
+    for (int i = 0; i < MT; i++)
 #pragma unroll
-        for (int e = 0; e < 8; e++) {
-            const long long v = vq + e;
-            a[e] = (v < ve) ? dy[v * g.cout + co] : (bf16)0.0f;
+        for (int j = 0; j < 2 * KT; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int vl = lane & 31;  // the voxel of the chunk this lane stages
+    for (long long v0 = vb + 32LL * wave; v0 < ve; v0 += 128) {
+        const long long v = v0 + vl;
+        const bool inside = v < ve;
+        // dy rows of the chunk, transposed
+        for (int u = lane; u < 4 * cout; u += 64) {
+            const int c8 = (u >> 5) * 8;
+            bf16x8 val = inside ? *reinterpret_cast<const bf16x8 *>(dy + v * cout + c8) : zero8();
+#pragma unroll
+            for (int e = 0; e < 8; e++) dyT[(c8 + e) * WG_ROW + vl] = val[e];
         }
+        // x columns kbase .. kbase + 32 KT of the chunk's neighbours, transposed
+        const VoxPos pos = vox_pos(g, (int)(inside ? v : vb));
+        for (int u = lane; u < 128 * KT; u += 64) {
+            const int grp = u >> 5;
+            const int k8 = kbase + grp * 8;
+            bf16x8 val = zero8();
+            if (inside && k8 < K27) {
+                const int tap = k8 / cin, ci0 = k8 - tap * cin;
+                const int p = neighbour_at(g, pos, tap);
+                if (p >= 0) val = *reinterpret_cast<const bf16x8 *>(x + (long long)p * cin + ci0);
+            }
 #pragma unroll
-        for (int e = 0; e < 8; e++) {
-            const long long v = vq + e;
-            const VoxPos pos = vox_pos(g, (int)(v < ve ? v : vb));
+            for (int e = 0; e < 8; e++) xT[(grp * 8 + e) * WG_ROW + vl] = val[e];
+        }
+        // the wave's own LDS writes complete before its reads
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int r = lane & 15, q = (lane >> 4) * 8;
+        bf16x8 b[2 * KT];
 #pragma unroll
-            for (int j = 0; j < 2; j++) {
-                bf16 val = (bf16)0.0f;
-                if (v < ve && kcol[j] < K27) {
-                    const int p = neighbour_at(g, pos, tap[j]);
-                    if (p >= 0) val = x[(long long)p * g.cin + ci[j]];
+        for (int j = 0; j < 2 * KT; j++) b[j] = *reinterpret_cast<const bf16x8 *>(xT + (j * 16 + r) * WG_ROW + q);
+#pragma unroll
+        for (int i = 0; i < MT; i++) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(dyT + (i * 16 + r) * WG_ROW + q);
+#pragma unroll
+            for (int j = 0; j < 2 * KT; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[i][j], 0, 0, 0);
+        }
+        // the reads complete before the next chunk overwrites the staging area
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // the four waves' sums added in a fixed order through LDS (waves 2, 3
+    // into 0, 1, then 1 into 0), one partial per split: tile rows = output
+    // channels, columns = k
+    __syncthreads();
+    float *red = reinterpret_cast<float *>(smem_raw);  // [2][MT][2 KT][4][64]
+    constexpr int TILE = MT * 2 * KT * 4;
+    if (wave >= 2) {
+#pragma unroll
+        for (int i = 0; i < MT; i++)
+#pragma unroll
+            for (int j = 0; j < 2 * KT; j++)
+#pragma unroll
+                for (int rr = 0; rr < 4; rr++) red[(((wave - 2) * TILE) + (i * 2 * KT + j) * 4 + rr) * 64 + lane] = acc[i][j][rr];
+    }
+    __syncthreads();
+    if (wave < 2) {
+#pragma unroll
+        for (int i = 0; i < MT; i++)
+#pragma unroll
+            for (int j = 0; j < 2 * KT; j++)
+#pragma unroll
+                for (int rr = 0; rr < 4; rr++) acc[i][j][rr] += red[((wave * TILE) + (i * 2 * KT + j) * 4 + rr) * 64 + lane];
+    }
+    __syncthreads();
+    if (wave == 1) {
+#pragma unroll
+        for (int i = 0; i < MT; i++)
+#pragma unroll
+            for (int j = 0; j < 2 * KT; j++)
+#pragma unroll
+                for (int rr = 0; rr < 4; rr++) red[((i * 2 * KT + j) * 4 + rr) * 64 + lane] = acc[i][j][rr];
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int i = 0; i < MT; i++) {
+#pragma unroll
+            for (int j = 0; j < 2 * KT; j++) {
+                const int kc = kbase + j * 16 + (lane & 15);
+#pragma unroll
+                for (int rr = 0; rr < 4; rr++) {
+                    const float v = acc[i][j][rr] + red[((i * 2 * KT + j) * 4 + rr) * 64 + lane];
+                    const int orow = i * 16 + (lane >> 4) * 4 + rr;
+                    if (kc < g.kpad) partials[((long long)s * cout + orow) * g.kpad + kc] = v;
                 }
-                b[j][e] = val;
             }
         }
-#pragma unroll
-        for (int j = 0; j < 2; j++) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[j], 0, 0, 0);
     }
-    // tile rows = output channels, columns = k
-#pragma unroll
-    for (int j = 0; j < 2; j++)
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-            const int orow = cotile * 16 + (lane >> 4) * 4 + r;
-            const int kc = ktile * 32 + j * 16 + (lane & 15);
-            partials[((long long)s * g.cout + orow) * g.kpad + kc] = acc[j][r];
-        }
 }
 
 // fixed-order sum over splits; optional accumulate into dw
-__global__ void k_sum_splits(const float *__restrict__ partials, long long len, int splits, float *__restrict__ out) {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < len; i += (long long)gridDim.x * blockDim.x) {
-        float acc = 0.0f;
-        for (int s = 0; s < splits; s++) acc += partials[(long long)s * len + i];
-        out[i] = acc;
+// fixed-order sum over splits: a block of 256 threads takes 16 consecutive
+// outputs; thread (o, g) adds splits g, g + 16, g + 32, ... of output o in
+// that order, and the 16 group sums are added in group order
+constexpr int SUM_GROUPS = 16;
+__global__ void __launch_bounds__(256) k_sum_splits(const float *__restrict__ partials, long long len, int splits,
+                                                    float *__restrict__ out) {
+    __shared__ float red[SUM_GROUPS][256 / SUM_GROUPS];
+    const int o = threadIdx.x % (256 / SUM_GROUPS), grp = threadIdx.x / (256 / SUM_GROUPS);
+    const long long i = (long long)blockIdx.x * (256 / SUM_GROUPS) + o;
+    float acc = 0.0f;
+    if (i < len)
+        for (int s = grp; s < splits; s += SUM_GROUPS) acc += partials[(long long)s * len + i];
+    red[grp][o] = acc;
+    __syncthreads();
+    if (grp == 0 && i < len) {
+        float sum = 0.0f;
+        for (int k = 0; k < SUM_GROUPS; k++) sum += red[k][o];
+        out[i] = sum;
     }
 }
+
+static inline int sum_blocks(long long len) { return (int)((len + 256 / SUM_GROUPS - 1) / (256 / SUM_GROUPS)); }
 
 __global__ void k_sum_rows(const float *__restrict__ p, int rows, float scale, float *__restrict__ out) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -500,32 +585,72 @@ hipError_t nn_weight_flip(const void *w, int cin, int cout, int kpad, int kpad_t
     return hipGetLastError();
 }
 
+// k-tiles per block of the LDS weight gradient: KT * cout / 2 accumulator
+// registers, at most 64
+static inline int wgrad_kt(const ConvGeom &g) {
+    const int kt = g.cout > 64 ? 1 : (g.cout > 32 ? 2 : 4);
+    const int ktiles = g.kpad / 32;
+    return kt > ktiles ? (ktiles >= 2 ? 2 : 1) : kt;
+}
+
+// voxel splits of the weight gradient: about 1024 blocks (the fixed-order
+// sum over splits afterwards reads every split's partial), at least 128
+// voxels (one chunk per wave) per split
 int nn_wgrad_splits(const ConvGeom &g) {
     const long long nvox = (long long)g.n * g.D * g.H * g.W;
-    const long long tiles = (long long)(g.kpad / 32) * (g.cout / 16);
-    long long s = (4096 + tiles - 1) / tiles;
-    const long long maxs = (nvox + 31) / 32;
+    const int kt = wgrad_kt(g);
+    const long long kblocks = (g.kpad / 32 + kt - 1) / kt;
+    long long s = (1024 + kblocks - 1) / kblocks;
+    const long long maxs = (nvox + 127) / 128;
     if (s > maxs) s = maxs;
     if (s > 1024) s = 1024;
     return (int)(s < 1 ? 1 : s);
 }
 
+// partial sums the weight gradient leaves in its scratch (one per split)
+int nn_wgrad_partials(const ConvGeom &g) { return nn_wgrad_splits(g); }
+
 hipError_t nn_conv_wgrad(const void *x, const void *dy, const ConvGeom &g, int splits, float *partials, float *dw,
                          hipStream_t s) {
+    if (g.cout % 16 || g.cout > 128 || g.cin % 8) return hipErrorInvalidValue;
     const long long nvox = (long long)g.n * g.D * g.H * g.W;
     long long per = (nvox + splits - 1) / splits;
-    per = (per + 31) / 32 * 32;
-    const dim3 grid(g.kpad / 32, g.cout / 16, splits);
-    hipLaunchKernelGGL(k_conv_wgrad, grid, dim3(64), 0, s, (const bf16 *)x, (const bf16 *)dy, g, per, partials);
+    per = (per + 127) / 128 * 128;
+    const int kt = wgrad_kt(g);
+    const dim3 grid((g.kpad / 32 + kt - 1) / kt, splits);
+    const size_t sh = (size_t)4 * (g.cout + 32 * kt) * WG_ROW * sizeof(bf16);
+    const bf16 *xx = (const bf16 *)x, *dd = (const bf16 *)dy;
+#define WG_LAUNCH(MT, KT) hipLaunchKernelGGL((k_conv_wgrad_lds<MT, KT>), grid, dim3(256), sh, s, xx, dd, g, per, partials)
+    switch (g.cout / 16 * 8 + kt) {
+        case 8 + 4: WG_LAUNCH(1, 4); break;
+        case 8 + 2: WG_LAUNCH(1, 2); break;
+        case 8 + 1: WG_LAUNCH(1, 1); break;
+        case 16 + 4: WG_LAUNCH(2, 4); break;
+        case 16 + 2: WG_LAUNCH(2, 2); break;
+        case 16 + 1: WG_LAUNCH(2, 1); break;
+        case 24 + 4: WG_LAUNCH(3, 4); break;
+        case 24 + 2: WG_LAUNCH(3, 2); break;
+        case 24 + 1: WG_LAUNCH(3, 1); break;
+        case 32 + 4: WG_LAUNCH(4, 4); break;
+        case 32 + 2: WG_LAUNCH(4, 2); break;
+        case 32 + 1: WG_LAUNCH(4, 1); break;
+        default:
+            if (g.cout <= 80) WG_LAUNCH(5, 1);
+            else if (g.cout <= 96) WG_LAUNCH(6, 1);
+            else if (g.cout <= 112) WG_LAUNCH(7, 1);
+            else WG_LAUNCH(8, 1);
+            break;
+    }
+#undef WG_LAUNCH
     const long long len = (long long)g.cout * g.kpad;
-    hipLaunchKernelGGL(k_sum_splits, dim3(g1(len)), dim3(256), 0, s, partials, len, splits, dw);
+    hipLaunchKernelGGL(k_sum_splits, dim3(sum_blocks(len)), dim3(256), 0, s, partials, len, splits, dw);
     return hipGetLastError();
 }
 
 hipError_t nn_bias_grad(const void *dy, long long nvox, int c, int splits, float *partials, float *db, hipStream_t s) {
     long long per = (nvox + splits - 1) / splits;
     hipLaunchKernelGGL(k_bias_grad, dim3(splits), dim3(BIAS_THREADS), 0, s, (const bf16 *)dy, nvox, c, per, partials);
-    hipLaunchKernelGGL(k_sum_splits, dim3(1), dim3(256), 0, s, partials, (long long)c, splits, db);
+    hipLaunchKernelGGL(k_sum_splits, dim3(sum_blocks(c)), dim3(256), 0, s, partials, (long long)c, splits, db);
     return hipGetLastError();
 }
 
