@@ -60,7 +60,7 @@ def bytes_per_update(prec: str, storage: str) -> float:
 # workload, storage and launch shape (vec, bx, by, nt, map).  Drop an entry
 # whenever its kernel changes.
 MEASURED_TRAFFIC = {
-    ("braid256_f32", "moments", (4, 64, 4, 2, 1)): 563_175_266,
+    ("braid256_f32", "moments", (4, 64, 4, 2, 1)): 563_201_378,
     ("braid256_f32", "populations", (4, 64, 2, 3, 0)): 956_425_998,
 }
 

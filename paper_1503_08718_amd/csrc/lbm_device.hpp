@@ -563,6 +563,10 @@ __device__ __forceinline__ void pull_mom_exact(const Cell<float> &c, int xv, int
     Vec<float, VEC> Tzm = vload<float, VEC, NL>(sT + rzm), Zzm = vload<float, VEC, NL>(sZ + rzm);
     Vec<float, VEC> Tzp = vload<float, VEC, NL>(sT + rzp), Zzp = vload<float, VEC, NL>(sZ + rzp);
     load_phase<VEC>(c.phase + base, P.ph);
+    // every load of this node is in flight: back to the normal wave priority
+    // (the step kernel raises it on entry so the load issue of the waves
+    // resident on a SIMD is not interleaved with another wave's arithmetic)
+    __builtin_amdgcn_s_setprio(0);
     // x: the moments of my last node feed the next lane, of my first node the previous lane
     const int sl = min(max(xl.srcL, 0), 63), sr = min(max(xl.srcR, 0), 63);
     const float gotLT = __shfl(Tc.v[VEC - 1], sl, 64), gotLX = __shfl(Xc.v[VEC - 1], sl, 64);
