@@ -99,6 +99,8 @@ def parse():
     p.add_argument("--ref-out", default="", help="write the FP64 references to this JSON file")
     p.add_argument("--ref-in", default="", help="take the FP64 references from this JSON file instead of solving")
     p.add_argument("--max-steps", type=int, default=20_000_000)
+    p.add_argument("--inference-grid", default="isotropic", choices=["isotropic", "cube"],
+                   help="learned start: network grid with one coarsening factor on all axes, or always n^3")
     p.add_argument("--cells", type=int, default=64)
     p.add_argument("--seed", type=int, default=1503)
     p.add_argument("--model", default=os.path.join(ROOT, "paper_1503_08718_amd", "warmstart_model.pt"))
@@ -447,6 +449,7 @@ def mode_sweep(args):
     t_gen = time.perf_counter() - t_start
     net = ws.Net.from_file(args.model, batch=1) if "learned" in starts else None
     out = {"mode": "sweep", "cells": len(media), "solves_per_cell": 2, "tol": args.tol, "storage": args.storage,
+           "inference_grid": args.inference_grid,
            "nodes_total": int(sum(m.phase.size for m in media)), "seconds_geometry": round(t_gen, 2),
            "sizes": [list(m.phase.shape[::-1]) for m in media]}
     ref = None
@@ -479,7 +482,7 @@ def mode_sweep(args):
         t0 = time.perf_counter()
         _, res, setup, fb = ws.solve_fields(canon, tol=args.tol, start=start, net=net, batch=True,
                                             max_steps=args.max_steps, storage=args.storage, keep_fields=False,
-                                            tune=True)
+                                            tune=True, grid=args.inference_grid)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         steps = [r["steps"] for r in res]
@@ -488,6 +491,7 @@ def mode_sweep(args):
                "seconds": round(wall, 2), "setup_seconds": round(setup, 2),
                "cells_per_hour": round(len(media) / ((t_gen + wall) / 3600.0), 1),
                "steps_mean": float(np.mean(steps)), "steps_min_max": [min(steps), max(steps)],
+               "steps": steps,  # every solve, (x, z) per cell
                "effective_MLUPS": round(lu / max(wall - setup, 1e-9) / 1e6, 1),
                "k_T": [round(r["keff"], 6) for r in res[0::2]], "k_L": [round(r["keff"], 6) for r in res[1::2]]}
         if ref is not None:

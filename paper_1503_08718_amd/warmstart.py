@@ -75,7 +75,8 @@ class Net:
         L = load()
         self.L = L
         self.dev = torch.device(device)
-        self.n = n
+        self.n = n  # training grid n^3
+        self.grid = (n, n, n)  # (z, y, x) extents of the level-0 activations
         self.batch = batch
         self.stream = torch.cuda.current_stream(self.dev).cuda_stream
         rng = np.random.default_rng(seed)
@@ -97,42 +98,72 @@ class Net:
                 d[name] = torch.zeros_like(ref[name])
         self.t = 0
         self.rng_state = None  # batch-order generator state of train(), kept in checkpoints
+        self._store = None
         self._alloc(batch)
 
     # -- buffers -------------------------------------------------------------
+    _ACTS = (("x", 0, 8), ("a00", 0, 16), ("e0", 0, 16), ("p1", 1, 16), ("a10", 1, 32), ("e1", 1, 32),
+             ("p2", 2, 32), ("a20", 2, 64), ("e2", 2, 64), ("p3", 3, 64), ("a30", 3, 128),
+             ("e3", 3, 128), ("u2", 2, 128), ("b2", 2, 64), ("s2", 2, 64), ("d2", 2, 64),
+             ("u1", 1, 64), ("b1", 1, 32), ("s1", 1, 32), ("d1", 1, 32), ("u0", 0, 32),
+             ("b0", 0, 16), ("s0", 0, 16), ("d0", 0, 16), ("dout", 0, 16))
+
     def _alloc(self, batch):
-        n, dev, bf = self.n, self.dev, torch.bfloat16
+        """Activation, gradient and scratch buffers for the current grid.
+        Storage is kept between grids and only grown (the tensors used by
+        the layers are views of the first voxels of it), so that training
+        over cells of several shapes does not reallocate every iteration."""
+        (d0, h0, w0), dev, bf = self.grid, self.dev, torch.bfloat16
+        if batch != self.batch:
+            self._store = None
         self.batch = batch
-        vox = [batch * (n >> lv) ** 3 for lv in range(4)]
-        shape = {}
-        # forward activations (channels-last, flattened voxels)
-        for key, lv, c in (("x", 0, 8), ("a00", 0, 16), ("e0", 0, 16), ("p1", 1, 16), ("a10", 1, 32), ("e1", 1, 32),
-                           ("p2", 2, 32), ("a20", 2, 64), ("e2", 2, 64), ("p3", 3, 64), ("a30", 3, 128),
-                           ("e3", 3, 128), ("u2", 2, 128), ("b2", 2, 64), ("s2", 2, 64), ("d2", 2, 64),
-                           ("u1", 1, 64), ("b1", 1, 32), ("s1", 1, 32), ("d1", 1, 32), ("u0", 0, 32),
-                           ("b0", 0, 16), ("s0", 0, 16), ("d0", 0, 16), ("dout", 0, 16)):
-            shape[key] = (vox[lv], c)
-        self.act = {k: torch.empty(v, dtype=bf, device=dev) for k, v in shape.items()}
-        # gradient buffers, one per activation shape class
-        self.grad = {k: torch.empty(v, dtype=bf, device=dev) for k, v in shape.items()}
-        self.tmp = {lv: torch.empty((vox[lv], 128), dtype=bf, device=dev) for lv in range(4)}
-        self.out = torch.empty((vox[0], 16), dtype=torch.float32, device=dev)
-        self.target = torch.empty(vox[0], dtype=torch.float32, device=dev)
-        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
-        self.mse_scratch = torch.empty(1024, dtype=torch.float32, device=dev)
-        wt = max(cin * self.L.mrtlbm_nn_kpad(cout) for _, cin, cout, _ in LAYERS)
-        self.wt = torch.empty(wt, dtype=bf, device=dev)
+        vox = [batch * (d0 >> lv) * (h0 >> lv) * (w0 >> lv) for lv in range(4)]
         ws = 0
         for _, cin, cout, _ in LAYERS:
             for lv in range(4):
-                d = n >> lv
-                ws = max(ws, self.L.mrtlbm_nn_wgrad_scratch_bytes(batch, d, d, d, cin, cout))
-        self.wscratch = torch.empty(ws // 4 + 1, dtype=torch.float32, device=dev)
+                ws = max(ws, self.L.mrtlbm_nn_wgrad_scratch_bytes(batch, d0 >> lv, h0 >> lv, w0 >> lv, cin, cout))
+        st = getattr(self, "_store", None)
+        if st is None or st["vox"] < vox[0] or st["ws"] < ws:
+            cap = max(vox[0], st["vox"] if st else 0)
+            capv = [cap >> (3 * lv) for lv in range(4)]  # extents are multiples of 8: exact
+            wsb = max(ws, st["ws"] if st else 0)
+            st = {"vox": cap, "ws": wsb,
+                  # forward activations (channels-last, flattened voxels)
+                  "act": {k: torch.empty((capv[lv], c), dtype=bf, device=dev) for k, lv, c in self._ACTS},
+                  # gradient buffers, one per activation shape class
+                  "grad": {k: torch.empty((capv[lv], c), dtype=bf, device=dev) for k, lv, c in self._ACTS},
+                  "tmp": {lv: torch.empty((capv[lv], 128), dtype=bf, device=dev) for lv in range(4)},
+                  "out": torch.empty((cap, 16), dtype=torch.float32, device=dev),
+                  "target": torch.empty(cap, dtype=torch.float32, device=dev),
+                  "wscratch": torch.empty(wsb // 4 + 1, dtype=torch.float32, device=dev)}
+            self._store = st
+        lvl = {k: lv for k, lv, _ in self._ACTS}
+        self.act = {k: t[:vox[lvl[k]]] for k, t in st["act"].items()}
+        self.grad = {k: t[:vox[lvl[k]]] for k, t in st["grad"].items()}
+        self.tmp = {lv: t[:vox[lv]] for lv, t in st["tmp"].items()}
+        self.out = st["out"][:vox[0]]
+        self.target = st["target"][:vox[0]]
+        self.wscratch = st["wscratch"]
+        if not hasattr(self, "loss"):
+            self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+            self.mse_scratch = torch.empty(1024, dtype=torch.float32, device=dev)
+            wt = max(cin * self.L.mrtlbm_nn_kpad(cout) for _, cin, cout, _ in LAYERS)
+            self.wt = torch.empty(wt, dtype=bf, device=dev)
+
+    def set_grid(self, d: int, h: int, w: int):
+        """Run on a (d, h, w) = (z, y, x) grid instead of the training n^3
+        (the network is convolutional throughout; three 2x poolings need
+        extents that are multiples of 8)."""
+        if min(d, h, w) < 8 or (d | h | w) & 7:
+            raise ValueError(f"grid {d}x{h}x{w}: extents must be multiples of 8")
+        if (d, h, w) != self.grid:
+            self.grid = (d, h, w)
+            self._alloc(self.batch)
 
     # -- layer calls -------------------------------------------------------------
     def _dims(self, lv):
-        d = self.n >> lv
-        return self.batch, d, d, d
+        d, h, w = self.grid
+        return self.batch, d >> lv, h >> lv, w >> lv
 
     def _conv(self, name, src, dst, lv, out_f32=None):
         _, cin, cout, relu = next(l for l in LAYERS if l[0] == name)
@@ -253,21 +284,28 @@ class Net:
             check(self.L.mrtlbm_nn_adam(_p(self.b32[name]), _p(self.gb[name]), _p(self.mb[name]), _p(self.vb[name]),
                                         self.b32[name].numel(), lr, b1, b2, eps, self.t, None, self.stream))
 
-    def set_input(self, b: int, phase_dev: torch.Tensor, feat_dev: torch.Tensor):
-        n = self.n
-        dst = self.act["x"][b * n ** 3:(b + 1) * n ** 3]
-        check(self.L.mrtlbm_nn_features(_p(phase_dev), n, n, n, _p(feat_dev), _p(dst), self.stream))
+    def set_input(self, b: int, phase_dev: torch.Tensor, feat_dev: torch.Tensor, shape=None):
+        """Features of sample b of the batch from a cell of shape (z, y, x)
+        (default the training n^3), which becomes the network's grid."""
+        d, h, w = shape or (self.n,) * 3
+        self.set_grid(d, h, w)
+        nv = d * h * w
+        dst = self.act["x"][b * nv:(b + 1) * nv]
+        check(self.L.mrtlbm_nn_features(_p(phase_dev), d, h, w, _p(feat_dev), _p(dst), self.stream))
 
     # -- persistence -----------------------------------------------------------
-    def state_dict(self):
-        """Everything training needs to continue bit for bit: FP32 master
-        weights and biases, Adam's moments and step count, and the state of
-        the batch-order generator (set by train())."""
+    def state_dict(self, optimizer: bool = True):
+        """FP32 master weights and biases, and with optimizer (a training
+        checkpoint) everything training needs to continue bit for bit: Adam's
+        moments and step count and the state of the batch-order generator
+        (set by train())."""
         cpu = lambda d: {k: v.cpu() for k, v in d.items()}  # noqa: E731
-        sd = {"w": cpu(self.w32), "b": cpu(self.b32), "n": self.n, "t": self.t,
-              "adam": {"mw": cpu(self.mw), "vw": cpu(self.vw), "mb": cpu(self.mb), "vb": cpu(self.vb)}}
-        if self.rng_state is not None:
-            sd["rng"] = self.rng_state
+        sd = {"w": cpu(self.w32), "b": cpu(self.b32), "n": self.n}
+        if optimizer:
+            sd["t"] = self.t
+            sd["adam"] = {"mw": cpu(self.mw), "vw": cpu(self.vw), "mb": cpu(self.mb), "vb": cpu(self.vb)}
+            if self.rng_state is not None:
+                sd["rng"] = self.rng_state
         return sd
 
     def load_state_dict(self, sd):
@@ -282,8 +320,8 @@ class Net:
         self.t = int(sd.get("t", 0))
         self.rng_state = sd.get("rng")
 
-    def save(self, path):
-        torch.save(self.state_dict(), path)
+    def save(self, path, optimizer: bool = True):
+        torch.save(self.state_dict(optimizer), path)
 
     @classmethod
     def from_file(cls, path, batch=1, device="cuda:0"):
@@ -328,12 +366,13 @@ def linear_start(shape, device, dtype=torch.float32):
 
 
 def solve_fields(media, tol=1e-4, check_every=1000, max_steps=5_000_000, start="linear", net=None, batch=True,
-                 precision="f32", storage="populations", keep_fields=True, tune=False):
+                 precision="f32", storage="populations", keep_fields=True, tune=False, grid="isotropic"):
     """Steady x-gradient fields of canonical media (periodic sides).
 
-    start: "zero", "linear" or "learned" (needs net); tune: pick the batched
-    step's shape for this set first (batch only).  Returns (temperature
-    tensors or None, results, setup seconds, number of rejected predictions)."""
+    start: "zero", "linear" or "learned" (needs net; grid: the inference grid
+    of predict_start); tune: pick the batched step's shape for this set first
+    (batch only).  Returns (temperature tensors or None, results, setup
+    seconds, number of rejected predictions)."""
     from .solver import Medium, batch_autotune, batch_solve
 
     cells = []
@@ -351,7 +390,7 @@ def solve_fields(media, tol=1e-4, check_every=1000, max_steps=5_000_000, start="
         elif start == "linear":
             g.init(linear_start(g.shape, g.device), flux=True)
         else:
-            T0, bad = predict_start(net, m, g)
+            T0, bad = predict_start(net, m, g, grid)
             if bad:
                 fallbacks += 1
                 g.init()
@@ -367,50 +406,79 @@ def solve_fields(media, tol=1e-4, check_every=1000, max_steps=5_000_000, start="
     return temps, res, setup, fallbacks
 
 
-def predict_start(net: Net, m, g) -> tuple[torch.Tensor, int]:
+def inference_grid(shape, n: int) -> tuple[int, int, int]:
+    """(z, y, x) grid the network runs on for a cell of shape (nz, ny, nx):
+    one common coarsening factor, max(shape) / n, on every axis (so that the
+    voxels stay as nearly cubic as extents that are multiples of 8 allow and
+    the largest extent is the training size n), each extent rounded to a
+    multiple of 8, at least 8."""
+    f = max(shape) / n
+    return tuple(max(8, int(round(e / f / 8.0)) * 8) for e in shape)
+
+
+def predict_start(net: Net, m, g, grid: str = "isotropic") -> tuple[torch.Tensor, int]:
     """Network start field for medium m on solver medium g (x gradient).
-    The cell is resampled to the network's n^3 grid (a box average of the
+    The cell is resampled to the inference grid (a box average of the
     per-voxel features, with the tensors mapped to the new voxel spacing),
     and the prediction is interpolated back to the cell's own grid.
+    grid: "isotropic" (inference_grid: one coarsening factor on all axes) or
+    "cube" (the training n^3 whatever the cell's shape).
     Returns (T0, number of rejected values)."""
     L = net.L
-    n = net.n
     nz, ny, nx = m.phase.shape
+    if grid == "isotropic":
+        dc, hc, wc = inference_grid((nz, ny, nx), net.n)
+    elif grid == "cube":
+        dc = hc = wc = net.n
+    else:
+        raise ValueError(f"unknown inference grid {grid!r}")
+    net.set_grid(dc, hc, wc)
     s = net.stream
-    feat = torch.from_numpy(feature_table(m.k, (nx / n, ny / n, nz / n))).to(net.dev)
-    check(L.mrtlbm_nn_features_resampled(_p(g.phase), nz, ny, nx, _p(feat), n, n, n, _p(net.act["x"]), s))
+    feat = torch.from_numpy(feature_table(m.k, (nx / wc, ny / hc, nz / dc))).to(net.dev)
+    check(L.mrtlbm_nn_features_resampled(_p(g.phase), nz, ny, nx, _p(feat), dc, hc, wc, _p(net.act["x"]), s))
     net.forward()
     T0 = torch.empty((nz, ny, nx), dtype=torch.float32, device=net.dev)
     bad_scratch = torch.empty(2048, dtype=torch.int32, device=net.dev)
     bad = ctypes.c_longlong()
-    check(L.mrtlbm_nn_to_temperature(_p(net.out), 16, n, n, n, nz, ny, nx, SCALE, MARGIN, _p(T0), _p(bad_scratch),
-                                     ctypes.byref(bad), s))
+    check(L.mrtlbm_nn_to_temperature(_p(net.out), 16, dc, hc, wc, nz, ny, nx, SCALE, MARGIN, _p(T0),
+                                     _p(bad_scratch), ctypes.byref(bad), s))
     return T0, bad.value
 
 
-def make_dataset(media, size=64, tol=1e-5, chunk=128, log=print):
+def make_dataset(media, size=None, tol=1e-5, chunk=128, log=print):
     """Steady fields of braided cells (already voxelised); each cell gives two
-    samples (x- and z-solve, canonicalised).  Returns device tensors (phases
-    uint8 [S, size^3], feature tables [S, nphase, 6], targets [S, size^3])
-    and statistics."""
+    samples (x- and z-solve, canonicalised).  Returns the samples grouped by
+    shape, as a list of (shape (z, y, x), phases uint8 [S, voxels], feature
+    tables [S, nphase, 6], targets [S, voxels]) on the device, and
+    statistics.  (size is accepted for the older cubic call and ignored.)"""
     canon = [mm for m in media for mm in canonical_media(m)]
-    phases, feats, targets = [], [], []
+    groups = {}
     steps = []
     t0 = time.perf_counter()
     for c0 in range(0, len(canon), chunk):
         part = canon[c0:c0 + chunk]
         temps, res, _, _ = solve_fields(part, tol=tol, start="linear", storage="moments")
         for m, T, r in zip(part, temps, res):
-            tgt = torch.empty(size ** 3, dtype=torch.float32, device=T.device)
-            check(load().mrtlbm_nn_target(_p(T), size, size, size, SCALE, _p(tgt),
-                                          torch.cuda.current_stream().cuda_stream))
-            phases.append(torch.from_numpy(m.phase.reshape(-1)).to(T.device))
-            feats.append(torch.from_numpy(feature_table(m.k)).to(T.device))
-            targets.append(tgt)
+            d, h, w = m.phase.shape
+            tgt = torch.empty(d * h * w, dtype=torch.float32, device=T.device)
+            check(load().mrtlbm_nn_target(_p(T), d, h, w, SCALE, _p(tgt), torch.cuda.current_stream().cuda_stream))
+            gr = groups.setdefault((d, h, w), ([], [], []))
+            gr[0].append(torch.from_numpy(m.phase.reshape(-1)).to(T.device))
+            gr[1].append(torch.from_numpy(feature_table(m.k)).to(T.device))
+            gr[2].append(tgt)
             steps.append(r["steps"])
         log(f"dataset: {min(c0 + chunk, len(canon))}/{len(canon)} fields, {time.perf_counter() - t0:.1f} s")
-    return (torch.stack(phases), torch.stack(feats), torch.stack(targets)), dict(
-        seconds=time.perf_counter() - t0, mean_steps=float(np.mean(steps)))
+    data = [(shape, torch.stack(g[0]), torch.stack(g[1]), torch.stack(g[2])) for shape, g in sorted(groups.items())]
+    return data, dict(seconds=time.perf_counter() - t0, mean_steps=float(np.mean(steps)),
+                      shapes=len(data), samples=len(steps))
+
+
+def _groups(net: Net, data):
+    """Dataset as shape groups: a (phases, feats, targets) tuple of cubic
+    samples on the training grid is one group."""
+    if isinstance(data, tuple):
+        return [((net.n,) * 3,) + tuple(data)]
+    return list(data)
 
 
 # resolution level of each convolution (grid n >> level)
@@ -419,9 +487,12 @@ LEVEL = {"c00": 0, "c01": 0, "c10": 1, "c11": 1, "c20": 2, "c21": 2, "c30": 3, "
 
 
 def layer_flops(net: Net) -> dict:
-    """Algorithmic FLOPs of each convolution's forward pass:
-    2 * voxels * 27 * C_in * C_out (the K padding of the MFMA tiles not counted)."""
-    return {name: 2.0 * net.batch * (net.n >> LEVEL[name]) ** 3 * 27 * cin * cout for name, cin, cout, _ in LAYERS}
+    """Algorithmic FLOPs of each convolution's forward pass on the current
+    grid: 2 * voxels * 27 * C_in * C_out (the K padding of the MFMA tiles not
+    counted)."""
+    d, h, w = net.grid
+    return {name: 2.0 * net.batch * (d >> LEVEL[name]) * (h >> LEVEL[name]) * (w >> LEVEL[name]) * 27 * cin * cout
+            for name, cin, cout, _ in LAYERS}
 
 
 def forward_flops(net: Net) -> float:
@@ -437,52 +508,63 @@ def iteration_flops(net: Net) -> float:
 
 def train(net: Net, data, iters=2000, lr=1e-3, seed=0, log=print, log_every=100, horizon=None):
     """Adam iterations net.t + 1 .. iters, the learning rate decaying from lr
-    to lr / 10 over `horizon` iterations (default iters).  A network loaded
-    from a checkpoint continues where it stopped, with the same batches and
-    learning rates when given the same horizon."""
+    to lr / 10 over `horizon` iterations (default iters).  A batch is drawn
+    from one shape group (chosen with probability proportional to its size
+    when there are several), without replacement within it.  A network
+    loaded from a checkpoint continues where it stopped, with the same
+    batches and learning rates when given the same horizon."""
     horizon = horizon or iters
-    phases, feats, targets = data
-    S = phases.shape[0]
+    groups = _groups(net, data)
+    sizes = np.array([g[1].shape[0] for g in groups], dtype=np.float64)
+    if any(sz < net.batch for sz in sizes):
+        raise ValueError(f"a shape group has fewer samples than the batch ({net.batch})")
     rng = np.random.default_rng(seed)
     if net.rng_state is not None:
         rng.bit_generator.state = net.rng_state
-    nv = net.n ** 3
     losses = []
     t0 = time.perf_counter()
     first = net.t + 1
+    flops = 0.0
     for it in range(first, iters + 1):
-        idx = rng.choice(S, size=net.batch, replace=False)
+        gi = 0 if len(groups) == 1 else int(rng.choice(len(groups), p=sizes / sizes.sum()))
+        shape, phases, feats, targets = groups[gi]
+        idx = rng.choice(phases.shape[0], size=net.batch, replace=False)
         net.rng_state = rng.bit_generator.state
+        nv = shape[0] * shape[1] * shape[2]
         for b, i in enumerate(idx):
-            net.set_input(b, phases[i], feats[i])
+            net.set_input(b, phases[i], feats[i], shape)
             net.target[b * nv:(b + 1) * nv].copy_(targets[i])
         net.forward()
         net.loss_and_grad()
         net.backward()
         cur_lr = lr * (0.1 ** (it / horizon))  # exponential decay to lr / 10
         net.adam(lr=cur_lr)
+        flops += iteration_flops(net)
         if it % log_every == 0 or it == iters:
             loss = float(net.loss.item())
             losses.append((it, loss))
             dt = time.perf_counter() - t0
-            log(f"train it {it}: loss {loss:.3e}  ({dt:.1f} s, "
-                f"{iteration_flops(net) * (it - first + 1) / dt / 1e12:.2f} TFLOP/s)")
+            log(f"train it {it}: loss {loss:.3e}  ({dt:.1f} s, {flops / dt / 1e12:.2f} TFLOP/s)")
     return losses
 
 
 def evaluate(net: Net, data) -> float:
-    phases, feats, targets = data
-    nv = net.n ** 3
-    tot = 0.0
-    S = phases.shape[0]
-    for i0 in range(0, S - S % net.batch, net.batch):
-        for b in range(net.batch):
-            net.set_input(b, phases[i0 + b], feats[i0 + b])
-            net.target[b * nv:(b + 1) * nv].copy_(targets[i0 + b])
-        net.forward()
-        net.loss_and_grad()
-        tot += float(net.loss.item())
-    return tot / max(1, S // net.batch)
+    """Mean loss over the batches of every shape group, in order; a group's
+    last batch is filled up with its first samples again."""
+    tot, nb = 0.0, 0
+    for shape, phases, feats, targets in _groups(net, data):
+        nv = shape[0] * shape[1] * shape[2]
+        S = phases.shape[0]
+        for i0 in range(0, S, net.batch):
+            for b in range(net.batch):
+                i = (i0 + b) % S
+                net.set_input(b, phases[i], feats[i], shape)
+                net.target[b * nv:(b + 1) * nv].copy_(targets[i])
+            net.forward()
+            net.loss_and_grad()
+            tot += float(net.loss.item())
+            nb += 1
+    return tot / max(1, nb)
 
 
 def bench(args) -> dict:
@@ -555,36 +637,49 @@ def main():
     import json
 
     p = argparse.ArgumentParser(description="generate data, train and save the warm-start network")
-    p.add_argument("--cells", type=int, default=1000, help="training cells (two fields each: x and z solves)")
+    p.add_argument("--cells", type=int, default=1000, help="cubic training cells (two fields each: x and z solves)")
+    p.add_argument("--mixed-cells", type=int, default=1000,
+                   help="training cells whose extents are drawn per axis from --mixed-sizes")
+    p.add_argument("--mixed-sizes", default="32,40,48,64")
     p.add_argument("--tol", type=float, default=1e-5, help="k_eff tolerance of the target fields")
     p.add_argument("--val-cells", type=int, default=16)
     p.add_argument("--size", type=int, default=64)
-    p.add_argument("--iters", type=int, default=4000)
+    p.add_argument("--iters", type=int, default=40000)
     p.add_argument("--batch", type=int, default=4)
     p.add_argument("--lr", type=float, default=1e-3)
-    p.add_argument("--out", default=os.path.join(os.path.dirname(__file__), "warmstart_model.pt"))
+    p.add_argument("--out", default=os.path.join(os.path.dirname(__file__), "warmstart_model.pt"),
+                   help="the trained weights (what inference loads)")
+    p.add_argument("--checkpoint", default="", help="also write a full training checkpoint (Adam state, batch order)")
     p.add_argument("--workers", type=int, default=8)
     a = p.parse_args()
     import workloads
 
     # voxelise every cell before the GPU is touched (forked workers)
-    train_media = generate_media(workloads.warmstart_cells(8718, a.cells, a.size), a.workers)
-    val_media = generate_media(workloads.warmstart_cells(8720, a.val_cells, a.size), a.workers)
+    sizes = tuple(int(v) for v in a.mixed_sizes.split(",") if v)
+    train_specs = workloads.warmstart_cells(8718, a.cells, a.size)
+    val_specs = workloads.warmstart_cells(8720, a.val_cells, a.size)
+    if a.mixed_cells:
+        train_specs += workloads.warmstart_cells_mixed(8721, a.mixed_cells, sizes)
+        val_specs += workloads.warmstart_cells_mixed(8722, a.val_cells, sizes)
+    train_media = generate_media(train_specs, a.workers)
+    val_media = generate_media(val_specs, a.workers)
     _lib.load()
     _lib.set_progress(lambda msg: print(msg, flush=True), 30.0)
-    data, st = make_dataset(train_media, a.size, tol=a.tol)
-    val, _ = make_dataset(val_media, a.size, tol=a.tol)
+    data, st = make_dataset(train_media, tol=a.tol)
+    val, _ = make_dataset(val_media, tol=a.tol)
     net = Net(n=a.size, batch=a.batch, seed=0)
     before = evaluate(net, val)
     t0 = time.perf_counter()
     losses = train(net, data, iters=a.iters, lr=a.lr)
     t_train = time.perf_counter() - t0
     after = evaluate(net, val)
-    net.save(a.out)
-    print(json.dumps({"train_samples": int(data[0].shape[0]), "target_tol": a.tol,
+    net.save(a.out, optimizer=False)
+    if a.checkpoint:
+        net.save(a.checkpoint)
+    print(json.dumps({"train_samples": st["samples"], "shapes": st["shapes"], "target_tol": a.tol,
+                      "cubic_cells": a.cells, "mixed_cells": a.mixed_cells, "mixed_sizes": sizes,
                       "data_seconds": round(st["seconds"], 1),
                       "data_mean_steps": st["mean_steps"], "train_seconds": round(t_train, 1),
-                      "train_tflops": round(iteration_flops(net) * a.iters / t_train / 1e12, 3),
                       "val_loss_before": before, "val_loss_after": after, "losses": losses[-5:], "out": a.out}))
 
 

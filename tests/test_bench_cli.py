@@ -35,8 +35,40 @@ def test_network_flop_count():
 
     cc = [(64 ** 3, 1408), (32 ** 3, 4608), (16 ** 3, 18432), (8 ** 3, 24576)]
     fwd = 54.0 * sum(v * c for v, c in cc)
-    assert ws.forward_flops(types.SimpleNamespace(batch=1, n=64)) == fwd
-    assert ws.forward_flops(types.SimpleNamespace(batch=4, n=64)) == 4 * fwd
+    cube = (64, 64, 64)
+    assert ws.forward_flops(types.SimpleNamespace(batch=1, n=64, grid=cube)) == fwd
+    assert ws.forward_flops(types.SimpleNamespace(batch=4, n=64, grid=cube)) == 4 * fwd
     # training: forward + weight gradient everywhere, input gradient except the first layer
     first = 54.0 * 64 ** 3 * 8 * 16
-    assert ws.iteration_flops(types.SimpleNamespace(batch=1, n=64)) == 3 * fwd - first
+    assert ws.iteration_flops(types.SimpleNamespace(batch=1, n=64, grid=cube)) == 3 * fwd - first
+    # a 32 x 48 x 64 grid: every level has 32*48*64 / 64^3 of the cube's voxels
+    assert ws.forward_flops(types.SimpleNamespace(batch=1, n=64, grid=(32, 48, 64))) == fwd * 0.375
+
+
+def test_inference_grid():
+    """One coarsening factor, max extent / 64, on every axis; extents rounded
+    to multiples of 8: the sweep's shapes keep cubic (or, for a largest extent
+    of 96, nearly cubic) voxels, and cubic cells map to 64^3."""
+    from paper_1503_08718_amd.warmstart import inference_grid
+
+    assert inference_grid((64, 64, 64), 64) == (64, 64, 64)
+    assert inference_grid((128, 128, 128), 64) == (64, 64, 64)
+    assert inference_grid((96, 96, 96), 64) == (64, 64, 64)
+    assert inference_grid((128, 64, 96), 64) == (64, 32, 48)
+    assert inference_grid((64, 96, 128), 64) == (32, 48, 64)
+    assert inference_grid((96, 64, 64), 64) == (64, 40, 40)  # 42.7 -> 40
+    assert inference_grid((16, 16, 512), 64) == (8, 8, 64)  # at least 8
+    for shape in [(a, b, c) for a in (64, 96, 128) for b in (64, 96, 128) for c in (64, 96, 128)]:
+        g = inference_grid(shape, 64)
+        assert max(g) == 64 and all(e % 8 == 0 for e in g)
+        f = [s / e for s, e in zip(shape, g)]
+        assert max(f) / min(f) <= 1.07  # voxel aspect within 7 %
+
+
+def test_mixed_training_cells():
+    import workloads as w
+
+    c = w.warmstart_cells_mixed(8721, 200)
+    assert c == w.warmstart_cells_mixed(8721, 200)  # seeded
+    assert {x["nx"] for x in c} == {32, 40, 48, 64} and {x["nz"] for x in c} == {32, 40, 48, 64}
+    assert all(20.0 <= x["gamma"] <= 45.0 and 0.35 <= x["v"] <= 0.6 for x in c)

@@ -77,6 +77,37 @@ def test_learned_start_gain_on_held_out_128(ws):
             assert abs(a["keff"] - b["keff"]) < 1e-4 * abs(b["keff"]), (start, a["keff"], b["keff"])
 
 
+def test_learned_start_gain_on_uneven_cells(ws):
+    """Cells of uneven extent as the parametric sweep draws them (the first
+    two cells of its rng 1503: 64 x 128 x 96 and 96 x 64 x 64, never seen in
+    training), x and z solves, batched, to the production tolerance: the
+    network runs on a grid with one coarsening factor on every axis
+    (inference_grid), and the learned start must take fewer than half the
+    zero start's steps and land within 1e-4 of an FP64 solve from the zero
+    start."""
+    assert os.path.exists(MODEL)
+    media = [w.braid(c["nx"], c["ny"], c["nz"], c["gamma"], c["v"]) for c in w.sweep_cells(1503, 2)]
+    canon = [mm for m in media for mm in ws.canonical_media(m)]
+    assert {m.phase.shape for m in canon} == {(96, 128, 64), (64, 128, 96), (64, 64, 96), (96, 64, 64)}
+    net = ws.Net.from_file(MODEL, batch=1)
+    res = {}
+    for start in ("zero", "learned"):
+        _, r, _, fb = ws.solve_fields(canon, tol=1e-4, start=start, net=net, batch=True, storage="moments",
+                                      max_steps=20_000_000)
+        assert fb == 0 and all(x["converged"] for x in r), (start, r)
+        res[start] = r
+    zero = np.mean([r["steps"] for r in res["zero"]])
+    learned = np.mean([r["steps"] for r in res["learned"]])
+    print(f"uneven cells, mean steps to 1e-4: zero {zero:.0f}, learned {learned:.0f} ({zero / learned:.2f}x)")
+    assert learned < 0.5 * zero
+    _, ref, _, _ = ws.solve_fields(canon, tol=1e-6, start="zero", net=net, batch=True, precision="f64",
+                                   storage="moments", max_steps=20_000_000)
+    for start in ("zero", "learned"):
+        for a, b in zip(res[start], ref):
+            assert b["converged"]
+            assert abs(a["keff"] - b["keff"]) < 1e-4 * abs(b["keff"]), (start, a["keff"], b["keff"])
+
+
 def test_rejected_prediction_falls_back_to_zero_start(ws):
     import torch
 

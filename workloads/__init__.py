@@ -31,6 +31,7 @@ from .media import (  # noqa: F401
     random_spd,
     sweep_cells,
     warmstart_cells,
+    warmstart_cells_mixed,
 )
 from .unitcell import (  # noqa: F401
     PHI_Y_EXACT,

@@ -337,3 +337,16 @@ def warmstart_cells(seed: int, n: int, size: int):
     gam = rng.uniform(20.0, 45.0, n)
     vf = rng.uniform(0.35, 0.6, n)
     return [dict(nx=size, ny=size, nz=size, gamma=float(g), v=float(v)) for g, v in zip(gam, vf)]
+
+
+def warmstart_cells_mixed(seed: int, n: int, sizes=(32, 40, 48, 64)):
+    """Braided cells of uneven extent for the learned warm start's data: each
+    axis extent drawn uniformly from ``sizes`` (the grids that cells of the
+    parametric sweep are coarsened to for inference), braiding angle ~
+    U[20, 45] deg, yarn fraction ~ U[0.35, 0.6]."""
+    rng = np.random.default_rng(seed)
+    dims = rng.choice(np.asarray(sizes), size=(n, 3))
+    gam = rng.uniform(20.0, 45.0, n)
+    vf = rng.uniform(0.35, 0.6, n)
+    return [dict(nx=int(d[0]), ny=int(d[1]), nz=int(d[2]), gamma=float(g), v=float(v))
+            for d, g, v in zip(dims, gam, vf)]
