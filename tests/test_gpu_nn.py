@@ -278,15 +278,18 @@ TEACHER = {
 }
 
 
-def _trained_net_pass(env, n=32):
+def _trained_net_pass(env, n=32, grid=None):
     L, torch = env
     from paper_1503_08718_amd import warmstart as ws
 
     net = ws.Net(n=n, batch=1, seed=3)
+    if grid is not None:
+        net.set_grid(*grid)
+    nv = int(np.prod(net.grid))
     rng = np.random.default_rng(11)
-    xd, x = bf(torch, np.concatenate([rng.uniform(-1, 1, (n ** 3, 7)), np.zeros((n ** 3, 1))], axis=1))
+    xd, x = bf(torch, np.concatenate([rng.uniform(-1, 1, (nv, 7)), np.zeros((nv, 1))], axis=1))
     net.act["x"].copy_(xd)
-    tgt = rng.uniform(-1, 1, n ** 3).astype(np.float32)
+    tgt = rng.uniform(-1, 1, nv).astype(np.float32)
     net.target.copy_(torch.tensor(tgt).cuda())
     net.forward()
     net.loss_and_grad()
@@ -300,8 +303,11 @@ def _trained_net_pass(env, n=32):
     return net, ws, x, tgt, W, B
 
 
-def test_every_layer_teacher_forced(env):
-    """Each of the 15 layers of one forward and backward pass at 32^3, fed
+@pytest.mark.parametrize("grid", [(32, 32, 32), (16, 24, 32)], ids=lambda g: "x".join(map(str, g)))
+def test_every_layer_teacher_forced(env, grid):
+    """Each of the 15 layers of one forward and backward pass, on the 32^3
+    training-shaped grid and on an uneven (z, y, x) = 16 x 24 x 32 grid such
+    as uneven cells are predicted on (coarse levels down to 2 x 3 x 4), fed
     with the GPU's own stored BF16 input activation and upstream gradient:
     the FP64 oracle's output, input gradient (BF16 on the GPU: relative L2
     <= 1e-2, cosine >= 0.999) and weight and bias gradients (FP32 on the GPU
@@ -309,13 +315,13 @@ def test_every_layer_teacher_forced(env):
     layer by layer, so that an indexing or adjoint fault in any one layer
     cannot hide behind the BF16 rounding of the layers before it."""
     L, torch = env
-    net, ws, _, _, W, B = _trained_net_pass(env)
-    n = net.n
+    net, ws, _, _, W, B = _trained_net_pass(env, grid=grid)
+    assert net.grid == grid
     circ = (False, True, True)
 
     def host(t, lv, c):
-        d = n >> lv
-        return t.float().cpu().numpy().astype(np.float64).reshape(1, d, d, d, -1)[..., :c]
+        d, h, w = (e >> lv for e in grid)
+        return t.float().cpu().numpy().astype(np.float64).reshape(1, d, h, w, -1)[..., :c]
 
     report = []
     for name, cin, cout, relu in ws.LAYERS:
@@ -329,7 +335,7 @@ def test_every_layer_teacher_forced(env):
             assert rel_l2(y_gpu, y_ref) <= 1e-2 and cosine(y_gpu, y_ref) >= 0.999, (name, "forward")
             dpre = _q(dy * (y_gpu > 0))  # the GPU's own ReLU decisions
         else:
-            out = net.out.cpu().numpy().astype(np.float64).reshape(1, n, n, n, cout)
+            out = net.out.cpu().numpy().astype(np.float64).reshape((1,) + grid + (cout,))
             assert rel_l2(out, y_or) <= 1e-4, (name, "forward")
             dpre = dy
         dx, dw, db = C.conv3d_backward(xin, W[name], dpre, circ)
