@@ -646,7 +646,7 @@ def main():
     p.add_argument("--size", type=int, default=64)
     p.add_argument("--iters", type=int, default=40000)
     p.add_argument("--batch", type=int, default=4)
-    p.add_argument("--lr", type=float, default=1e-3)
+    p.add_argument("--lr", type=float, default=5e-4)
     p.add_argument("--out", default=os.path.join(os.path.dirname(__file__), "warmstart_model.pt"),
                    help="the trained weights (what inference loads)")
     p.add_argument("--checkpoint", default="", help="also write a full training checkpoint (Adam state, batch order)")
