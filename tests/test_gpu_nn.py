@@ -491,3 +491,35 @@ def test_training_resumes_bit_for_bit(env, tmp_path):
         assert torch.equal(a.w32[name], c.w32[name]), name
         assert torch.equal(a.b32[name], c.b32[name]), name
         assert torch.equal(a.vw[name], c.vw[name]), name
+
+
+def test_training_over_shape_groups(env):
+    """Training data of two cell shapes (a 16^3 group and an uneven
+    (z, y, x) = 8 x 16 x 24 group): every batch comes from one group, the
+    network switches grids between iterations, and the run is deterministic
+    -- two fresh networks trained alike end with identical weights; the
+    grouped evaluation is finite."""
+    L, torch = env
+    from paper_1503_08718_amd import warmstart as ws
+
+    g = torch.Generator().manual_seed(8)
+    data = []
+    for shape, S in (((16, 16, 16), 3), ((8, 16, 24), 4)):
+        nv = shape[0] * shape[1] * shape[2]
+        data.append((shape, torch.randint(0, 3, (S, nv), generator=g, dtype=torch.uint8).cuda(),
+                     (torch.rand((S, 3, 6), generator=g) - 0.5).cuda(),
+                     (torch.rand((S, nv), generator=g) * 0.2).cuda()))
+    quiet = lambda *a, **k: None  # noqa: E731
+    nets = []
+    for _ in range(2):
+        net = ws.Net(n=16, batch=2, seed=5)
+        ws.train(net, data, iters=8, seed=3, log=quiet)
+        nets.append(net)
+    torch.cuda.synchronize()
+    for name, _, _, _ in ws.LAYERS:
+        assert torch.equal(nets[0].w32[name], nets[1].w32[name]), name
+    loss = ws.evaluate(nets[0], data)
+    assert np.isfinite(loss) and loss > 0
+    with pytest.raises(ValueError):
+        ws.train(ws.Net(n=16, batch=4, seed=5), data, iters=1, log=quiet)  # a group smaller than the batch
+
