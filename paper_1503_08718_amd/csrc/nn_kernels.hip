@@ -119,6 +119,114 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const bf16 *__restrict__ in, c
         }
 }
 
+// neighbour of a voxel at offset (dx, dy, dz) in {-1, 0, 1}^3, or -1 if it
+// falls into zero padding; selects instead of branches
+__device__ __forceinline__ int neighbour_off(const ConvGeom &g, const VoxPos &p, int dx, int dy, int dz) {
+    int px = p.x + dx, py = p.y + dy, pz = p.z + dz;
+    const bool ox = px < 0 || px >= g.W, oy = py < 0 || py >= g.H, oz = pz < 0 || pz >= g.D;
+    px += px < 0 ? g.W : (px >= g.W ? -g.W : 0);
+    py += py < 0 ? g.H : (py >= g.H ? -g.H : 0);
+    pz += pz < 0 ? g.D : (pz >= g.D ? -g.D : 0);
+    const bool ok = (!ox || (g.circ & 1)) && (!oy || (g.circ & 2)) && (!oz || (g.circ & 4));
+    return ok ? ((p.nb * g.D + pz) * g.H + py) * g.W + px : -1;
+}
+
+// k_conv_fwd for a channel count known at compile time (8, 16, 32, 64 or
+// 128): the tap and channel of a lane's k are shifts and masks, and with 32
+// or more channels (whole 32-wide k-chunks per tap) each tile's neighbour
+// is found once per tap instead of once per chunk.  Same tiles, operands
+// and accumulation order as k_conv_fwd, so the same results bit for bit.
+template <int MT, int NT, int CIN>
+__global__ void __launch_bounds__(256) k_conv_fwd_c(const bf16 *__restrict__ in, const bf16 *__restrict__ w,
+                                                    const float *__restrict__ bias, ConvGeom g, int relu,
+                                                    bf16 *__restrict__ out, float *__restrict__ out_f32) {
+    static_assert(CIN == 8 || CIN == 16 || CIN % 32 == 0, "channel count");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long long nvox = (long long)g.n * g.D * g.H * g.W;
+    const long long v0 = ((long long)blockIdx.x * 4 + wave) * (16 * MT);
+    const int n0 = blockIdx.y * (16 * NT);
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int i = 0; i < MT; i++)
+#pragma unroll
+        for (int j = 0; j < NT; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    VoxPos vrow[MT];
+#pragma unroll
+    for (int i = 0; i < MT; i++) {
+        const long long v = v0 + i * 16 + (lane & 15);
+        vrow[i] = vox_pos(g, (int)(v < nvox ? v : nvox - 1));
+    }
+    const int kq = (lane >> 4) * 8;  // this lane's first k inside a 32-wide chunk
+    const bf16 *wrow[NT];
+#pragma unroll
+    for (int j = 0; j < NT; j++) wrow[j] = w + (long long)(n0 + j * 16 + (lane & 15)) * g.kpad + kq;
+    if constexpr (CIN >= 32) {
+        for (int tap = 0; tap < 27; tap++) {
+            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+            const bf16 *src[MT];
+#pragma unroll
+            for (int i = 0; i < MT; i++) {
+                const int p = neighbour_off(g, vrow[i], dx, dy, dz);
+                src[i] = p >= 0 ? in + (long long)p * CIN + kq : nullptr;
+            }
+#pragma unroll
+            for (int c = 0; c < CIN / 32; c++) {
+                bf16x8 a[MT], b[NT];
+#pragma unroll
+                for (int i = 0; i < MT; i++)
+                    a[i] = src[i] ? *reinterpret_cast<const bf16x8 *>(src[i] + c * 32) : zero8();
+#pragma unroll
+                for (int j = 0; j < NT; j++)
+                    b[j] = *reinterpret_cast<const bf16x8 *>(wrow[j] + tap * CIN + c * 32);
+#pragma unroll
+                for (int i = 0; i < MT; i++)
+#pragma unroll
+                    for (int j = 0; j < NT; j++)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+            }
+        }
+    } else {
+        // a 32-wide chunk spans 32 / CIN taps; this lane's 8 channels belong
+        // to tap TPC * q + sub of chunk q (tap 27 and beyond: zero padding)
+        constexpr int TPC = 32 / CIN;
+        const int sub = kq / CIN, c0 = kq % CIN;
+#pragma unroll
+        for (int q = 0; q < (27 + TPC - 1) / TPC; q++) {
+            const int tap = q * TPC + sub;
+            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+            bf16x8 a[MT], b[NT];
+#pragma unroll
+            for (int i = 0; i < MT; i++) {
+                const int p = tap < 27 ? neighbour_off(g, vrow[i], dx, dy, dz) : -1;
+                a[i] = p >= 0 ? *reinterpret_cast<const bf16x8 *>(in + (long long)p * CIN + c0) : zero8();
+            }
+#pragma unroll
+            for (int j = 0; j < NT; j++) b[j] = *reinterpret_cast<const bf16x8 *>(wrow[j] + q * 32);
+#pragma unroll
+            for (int i = 0; i < MT; i++)
+#pragma unroll
+                for (int j = 0; j < NT; j++)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < MT; i++)
+#pragma unroll
+        for (int j = 0; j < NT; j++) {
+            const int co = n0 + j * 16 + (lane & 15);
+            const float bb = bias ? bias[co] : 0.0f;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const long long v = v0 + i * 16 + (lane >> 4) * 4 + r;
+                if (v >= nvox) continue;
+                float y = acc[i][j][r] + bb;
+                if (relu) y = fmaxf(y, 0.0f);
+                if (out_f32) out_f32[v * g.cout + co] = y;
+                else out[v * g.cout + co] = (bf16)y;
+            }
+        }
+}
+
 // weights of the adjoint convolution: wt[ci][flip(tap) * cout + co] = w[co][tap * cin + ci]
 __global__ void k_weight_flip(const bf16 *__restrict__ w, int cin, int cout, int kpad, int kpad_t, bf16 *__restrict__ wt) {
     const long long total = (long long)cin * kpad_t;
@@ -573,9 +681,23 @@ hipError_t nn_conv_fwd(const void *in, const void *w, const float *bias, const C
     const bf16 *i = (const bf16 *)in;
     const bf16 *ww = (const bf16 *)w;
     bf16 *o = (bf16 *)out;
-    if (nt == 4) hipLaunchKernelGGL((k_conv_fwd<2, 4>), grid, block, 0, s, i, ww, bias, g, relu, o, out_f32);
-    else if (nt == 2) hipLaunchKernelGGL((k_conv_fwd<2, 2>), grid, block, 0, s, i, ww, bias, g, relu, o, out_f32);
-    else hipLaunchKernelGGL((k_conv_fwd<2, 1>), grid, block, 0, s, i, ww, bias, g, relu, o, out_f32);
+#define FWD_C(NT_, CIN_) \
+    hipLaunchKernelGGL((k_conv_fwd_c<2, NT_, CIN_>), grid, block, 0, s, i, ww, bias, g, relu, o, out_f32)
+#define FWD_NT(NT_)                                                                           \
+    switch (g.cin) {                                                                          \
+        case 8: FWD_C(NT_, 8); break;                                                         \
+        case 16: FWD_C(NT_, 16); break;                                                       \
+        case 32: FWD_C(NT_, 32); break;                                                       \
+        case 64: FWD_C(NT_, 64); break;                                                       \
+        case 128: FWD_C(NT_, 128); break;                                                     \
+        default:                                                                              \
+            hipLaunchKernelGGL((k_conv_fwd<2, NT_>), grid, block, 0, s, i, ww, bias, g, relu, o, out_f32); \
+    }
+    if (nt == 4) { FWD_NT(4) }
+    else if (nt == 2) { FWD_NT(2) }
+    else { FWD_NT(1) }
+#undef FWD_NT
+#undef FWD_C
     return hipGetLastError();
 }
 
