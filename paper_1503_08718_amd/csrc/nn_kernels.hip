@@ -442,6 +442,30 @@ __global__ void k_add(const bf16 *__restrict__ a, const bf16 *__restrict__ b, bf
         out[i] = (bf16)((float)a[i] + (float)b[i]);
 }
 
+// the same on 8 channels (16 bytes) per thread; the launchers use these when
+// the counts are multiples of 8 and the arrays 16-byte aligned
+__global__ void k_relu_bwd8(const bf16x8 *__restrict__ y, const bf16x8 *__restrict__ dy, bf16x8 *__restrict__ dx,
+                            long long n8) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n8; i += (long long)gridDim.x * blockDim.x) {
+        const bf16x8 a = y[i], g = dy[i];
+        bf16x8 o;
+#pragma unroll
+        for (int e = 0; e < 8; e++) o[e] = ((float)a[e] > 0.0f) ? g[e] : (bf16)0.0f;
+        dx[i] = o;
+    }
+}
+
+__global__ void k_add8(const bf16x8 *__restrict__ a, const bf16x8 *__restrict__ b, bf16x8 *__restrict__ out,
+                       long long n8) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n8; i += (long long)gridDim.x * blockDim.x) {
+        const bf16x8 u = a[i], v = b[i];
+        bf16x8 o;
+#pragma unroll
+        for (int e = 0; e < 8; e++) o[e] = (bf16)((float)u[e] + (float)v[e]);
+        out[i] = o;
+    }
+}
+
 // 2x2x2 average pooling, channels-last; (D, H, W) are the input extents
 __global__ void k_pool2_fwd(const bf16 *__restrict__ in, int n, int D, int H, int W, int c, bf16 *__restrict__ out) {
     const int Do = D / 2, Ho = H / 2, Wo = W / 2;
@@ -488,6 +512,21 @@ __global__ void k_up2_fwd(const bf16 *__restrict__ in, int n, int D, int H, int 
         const int z = (int)(r % D2);
         const long long nb = r / D2;
         out[i] = in[(((nb * D + z / 2) * H + y / 2) * W + x / 2) * c + ch];
+    }
+}
+
+// k_up2_fwd on 8 channels per thread (c8 = c / 8 groups per voxel)
+__global__ void k_up2_fwd8(const bf16x8 *__restrict__ in, int n, int D, int H, int W, int c8, bf16x8 *__restrict__ out) {
+    const int D2 = 2 * D, H2 = 2 * H, W2 = 2 * W;
+    const long long total = (long long)n * D2 * H2 * W2 * c8;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
+        const int cg = (int)(i % c8);
+        long long r = i / c8;
+        const int x = (int)(r % W2); r /= W2;
+        const int y = (int)(r % H2); r /= H2;
+        const int z = (int)(r % D2);
+        const long long nb = r / D2;
+        out[i] = in[(((nb * D + z / 2) * H + y / 2) * W + x / 2) * c8 + cg];
     }
 }
 
@@ -672,31 +711,45 @@ static inline int g1(long long n) {
     return (int)(b > 16384 ? 16384 : (b < 1 ? 1 : b));
 }
 
+// Tiles of a wave: 16 * mt voxels x 16 * nt output channels.  Large tiles
+// reuse each gathered operand over more products, but a coarse level (8^3
+// voxels, 128 channels) then fills a few dozen blocks; tiles shrink until a
+// launch has 1024 blocks or they are 16 x 16.  Every output element sums the
+// same products in the same k order whatever the tile, so the results do
+// not depend on the choice.
 hipError_t nn_conv_fwd(const void *in, const void *w, const float *bias, const ConvGeom &g, int relu, void *out,
                        float *out_f32, hipStream_t s) {
     const long long nvox = (long long)g.n * g.D * g.H * g.W;
-    const long long vtiles = (nvox + 31) / 32;  // MT = 2
-    const int nt = (g.cout % 64 == 0) ? 4 : ((g.cout % 32 == 0) ? 2 : 1);
+    int mt = 2, nt = (g.cout % 64 == 0) ? 4 : ((g.cout % 32 == 0) ? 2 : 1);
+    auto blocks = [&](int m, int n) { return ((nvox + 16 * m - 1) / (16 * m) + 3) / 4 * (g.cout / (16 * n)); };
+    while (blocks(mt, nt) < 1024 && (nt > 1 || mt > 1)) {
+        if (nt > 1) nt >>= 1;
+        else mt = 1;
+    }
+    const long long vtiles = (nvox + 16 * mt - 1) / (16 * mt);
     const dim3 grid((unsigned)((vtiles + 3) / 4), g.cout / (16 * nt)), block(256);
     const bf16 *i = (const bf16 *)in;
     const bf16 *ww = (const bf16 *)w;
     bf16 *o = (bf16 *)out;
-#define FWD_C(NT_, CIN_) \
-    hipLaunchKernelGGL((k_conv_fwd_c<2, NT_, CIN_>), grid, block, 0, s, i, ww, bias, g, relu, o, out_f32)
-#define FWD_NT(NT_)                                                                           \
-    switch (g.cin) {                                                                          \
-        case 8: FWD_C(NT_, 8); break;                                                         \
-        case 16: FWD_C(NT_, 16); break;                                                       \
-        case 32: FWD_C(NT_, 32); break;                                                       \
-        case 64: FWD_C(NT_, 64); break;                                                       \
-        case 128: FWD_C(NT_, 128); break;                                                     \
-        default:                                                                              \
-            hipLaunchKernelGGL((k_conv_fwd<2, NT_>), grid, block, 0, s, i, ww, bias, g, relu, o, out_f32); \
+#define FWD_C(MT_, NT_, CIN_) \
+    hipLaunchKernelGGL((k_conv_fwd_c<MT_, NT_, CIN_>), grid, block, 0, s, i, ww, bias, g, relu, o, out_f32)
+#define FWD_T(MT_, NT_)                                                                                     \
+    switch (g.cin) {                                                                                        \
+        case 8: FWD_C(MT_, NT_, 8); break;                                                                  \
+        case 16: FWD_C(MT_, NT_, 16); break;                                                                \
+        case 32: FWD_C(MT_, NT_, 32); break;                                                                \
+        case 64: FWD_C(MT_, NT_, 64); break;                                                                \
+        case 128: FWD_C(MT_, NT_, 128); break;                                                              \
+        default: hipLaunchKernelGGL((k_conv_fwd<MT_, NT_>), grid, block, 0, s, i, ww, bias, g, relu, o, out_f32); \
     }
-    if (nt == 4) { FWD_NT(4) }
-    else if (nt == 2) { FWD_NT(2) }
-    else { FWD_NT(1) }
-#undef FWD_NT
+    if (mt == 2) {
+        if (nt == 4) { FWD_T(2, 4) }
+        else if (nt == 2) { FWD_T(2, 2) }
+        else { FWD_T(2, 1) }
+    } else {
+        FWD_T(1, 1)
+    }
+#undef FWD_T
 #undef FWD_C
     return hipGetLastError();
 }
@@ -776,13 +829,23 @@ hipError_t nn_bias_grad(const void *dy, long long nvox, int c, int splits, float
     return hipGetLastError();
 }
 
+static inline bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
 hipError_t nn_relu_bwd(const void *y, const void *dy, void *dx, long long n, hipStream_t s) {
-    hipLaunchKernelGGL(k_relu_bwd, dim3(g1(n)), dim3(256), 0, s, (const bf16 *)y, (const bf16 *)dy, (bf16 *)dx, n);
+    if (n % 8 == 0 && aligned16(y) && aligned16(dy) && aligned16(dx))
+        hipLaunchKernelGGL(k_relu_bwd8, dim3(g1(n / 8)), dim3(256), 0, s, (const bf16x8 *)y, (const bf16x8 *)dy,
+                           (bf16x8 *)dx, n / 8);
+    else
+        hipLaunchKernelGGL(k_relu_bwd, dim3(g1(n)), dim3(256), 0, s, (const bf16 *)y, (const bf16 *)dy, (bf16 *)dx, n);
     return hipGetLastError();
 }
 
 hipError_t nn_add(const void *a, const void *b, void *out, long long n, hipStream_t s) {
-    hipLaunchKernelGGL(k_add, dim3(g1(n)), dim3(256), 0, s, (const bf16 *)a, (const bf16 *)b, (bf16 *)out, n);
+    if (n % 8 == 0 && aligned16(a) && aligned16(b) && aligned16(out))
+        hipLaunchKernelGGL(k_add8, dim3(g1(n / 8)), dim3(256), 0, s, (const bf16x8 *)a, (const bf16x8 *)b,
+                           (bf16x8 *)out, n / 8);
+    else
+        hipLaunchKernelGGL(k_add, dim3(g1(n)), dim3(256), 0, s, (const bf16 *)a, (const bf16 *)b, (bf16 *)out, n);
     return hipGetLastError();
 }
 
@@ -795,7 +858,10 @@ hipError_t nn_pool2(int fwd, const void *in, int n, int D, int H, int W, int c, 
 
 hipError_t nn_up2(int fwd, const void *in, int n, int D, int H, int W, int c, void *out, hipStream_t s) {
     const long long small = (long long)n * D * H * W * c;
-    if (fwd) hipLaunchKernelGGL(k_up2_fwd, dim3(g1(small * 8)), dim3(256), 0, s, (const bf16 *)in, n, D, H, W, c, (bf16 *)out);
+    if (fwd && c % 8 == 0 && aligned16(in) && aligned16(out))
+        hipLaunchKernelGGL(k_up2_fwd8, dim3(g1(small)), dim3(256), 0, s, (const bf16x8 *)in, n, D, H, W, c / 8,
+                           (bf16x8 *)out);
+    else if (fwd) hipLaunchKernelGGL(k_up2_fwd, dim3(g1(small * 8)), dim3(256), 0, s, (const bf16 *)in, n, D, H, W, c, (bf16 *)out);
     else hipLaunchKernelGGL(k_up2_bwd, dim3(g1(small)), dim3(256), 0, s, (const bf16 *)in, n, D, H, W, c, (bf16 *)out);
     return hipGetLastError();
 }

@@ -98,6 +98,28 @@ def test_conv_forward(env, shape):
     assert rel_l2(got, r) < 1e-2 and cosine(got, r) > 0.999
 
 
+@pytest.mark.parametrize("cin,cout", [(64, 64), (128, 128), (16, 64)])
+def test_conv_tile_choice_leaves_results_unchanged(env, cin, cout):
+    """The launcher shrinks the tiles of a wave for small launches (8^3 x 1:
+    16 x 16 tiles) and keeps them large for big ones (64 copies of the same
+    grid): every copy's output equals the single grid's bit for bit, as each
+    output element sums the same products in the same k order."""
+    L, torch = env
+    D = H = W = 8
+    rng = np.random.default_rng(cin + cout)
+    xd, _ = bf(torch, rng.standard_normal((1, D, H, W, cin)))
+    wd, _ = bf(torch, pack_w(L, rng.standard_normal((cout, 3, 3, 3, cin)) * 0.2))
+    b = torch.tensor(rng.standard_normal(cout).astype(np.float32)).cuda()
+    one = torch.empty((D * H * W, cout), dtype=torch.float32, device="cuda")
+    assert L.mrtlbm_nn_conv3d_fwd(P(xd), 1, D, H, W, cin, P(wd), P(b), cout, 0b110, 0, None, P(one), None) == 0
+    many_in = xd.repeat(64, 1, 1, 1, 1).contiguous()
+    many = torch.empty((64 * D * H * W, cout), dtype=torch.float32, device="cuda")
+    assert L.mrtlbm_nn_conv3d_fwd(P(many_in), 64, D, H, W, cin, P(wd), P(b), cout, 0b110, 0, None, P(many),
+                                  None) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(many.view(64, D * H * W, cout), one.view(1, D * H * W, cout).expand(64, -1, -1))
+
+
 @pytest.mark.parametrize("shape", [s for s in SHAPES if s[4] % 16 == 0], ids=lambda s: "x".join(map(str, s[:6])))
 def test_conv_backward(env, shape):
     L, torch = env
@@ -150,6 +172,18 @@ def test_pool_upsample_add_relu(env):
     g = torch.empty_like(xd)
     assert L.mrtlbm_nn_relu_bwd(P(xd), P(xd), P(g), xd.numel(), None) == 0
     assert np.array_equal(g.float().cpu().numpy(), np.where(x > 0, x, 0))
+    # the one-element kernels behind the 8-channel ones: a count that is not
+    # a multiple of 8, and an output that is not 16-byte aligned
+    m = xd.numel() - 3
+    s2 = torch.empty_like(xd)
+    assert L.mrtlbm_nn_add(P(xd), P(xd), P(s2), m, None) == 0
+    assert np.array_equal(s2.float().cpu().numpy().ravel()[:m], 2 * x.ravel()[:m])
+    g2 = torch.empty_like(xd)
+    assert L.mrtlbm_nn_relu_bwd(P(xd), P(xd), P(g2), m, None) == 0
+    assert np.array_equal(g2.float().cpu().numpy().ravel()[:m], np.where(x > 0, x, 0).ravel()[:m])
+    up_u = torch.empty(n * D * H * W * c + 1, dtype=torch.bfloat16, device="cuda")
+    assert L.mrtlbm_nn_up2(1, P(yd), n, D // 2, H // 2, W // 2, c, ctypes.c_void_p(up_u.data_ptr() + 2), None) == 0
+    assert np.array_equal(up_u[1:].float().cpu().numpy().reshape(n, D, H, W, c), C.up2(y))
 
 
 def test_mse_and_adam(env):
