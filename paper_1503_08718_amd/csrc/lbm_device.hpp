@@ -235,6 +235,9 @@ __device__ __forceinline__ void pull_mom(const Cell<real> &c, int xv, int y, int
     Vec<real, VEC> Tzm = vload<real, VEC, NL>(sT + rzm), Zzm = vload<real, VEC, NL>(sZ + rzm);
     Vec<real, VEC> Tzp = vload<real, VEC, NL>(sT + rzp), Zzp = vload<real, VEC, NL>(sZ + rzp);
     load_phase<VEC>(c.phase + base, P.ph);
+    // all loads of this node are out: back to the normal wave priority (raised
+    // on entry to the moment step)
+    __builtin_amdgcn_s_setprio(0);
     // x: my last g1 feeds the next lane, my first g2 the previous lane
     const real mine1 = gplus(Tc.v[VEC - 1], Xc.v[VEC - 1]);
     const real mine2 = gminus(Tc.v[0], Xc.v[0]);
