@@ -445,12 +445,12 @@ def predict_start(net: Net, m, g, grid: str = "isotropic") -> tuple[torch.Tensor
     return T0, bad.value
 
 
-def make_dataset(media, size=None, tol=1e-5, chunk=128, log=print):
+def make_dataset(media, tol=1e-5, chunk=128, log=print):
     """Steady fields of braided cells (already voxelised); each cell gives two
     samples (x- and z-solve, canonicalised).  Returns the samples grouped by
     shape, as a list of (shape (z, y, x), phases uint8 [S, voxels], feature
     tables [S, nphase, 6], targets [S, voxels]) on the device, and
-    statistics.  (size is accepted for the older cubic call and ignored.)"""
+    statistics."""
     canon = [mm for m in media for mm in canonical_media(m)]
     groups = {}
     steps = []
